@@ -1,0 +1,101 @@
+"""Oracle (test infrastructure only): vertex patches, local spaces and colours
+(Sec. 3.1, Fig. smoother, Fig. hermite_type, Fig. patch_coloring).
+
+A patch is the set of the 2^d cells sharing an interior vertex v in
+{1..N-1}^d; its cells have coordinates {v_i - 1, v_i} in direction i.  Along
+direction i the patch carries 2n = 2k+2 nodes, patch-local index
+p = a (left cell, node a) or p = n + a (right cell, node a).
+
+Dirichlet local space V_j: the patch nodes minus those on the patch boundary
+that lie on an interior mesh face.  Per direction the kept set is
+{1..2k}, plus p = 0 when the patch touches the boundary x_i = 0 (v_i = 1) and
+plus p = 2k+1 when it touches x_i = 1 (v_i = N-1); boundary-of-domain nodes
+are kept so that they are smoothed at all.  V_j is the tensor product of the
+per-direction kept sets; the domain of dependence of the paper-literal kernel
+is all DoFs of the patch cells.
+
+Colours: colour(v) = sum_i ((v_i - 1) mod 2) 2^i, i.e. 2^d colours; patches of
+one colour share no cell, and colour 0 (all v_i odd) tiles the mesh by the
+children of the coarse cells.
+"""
+import itertools
+
+import numpy as np
+
+
+def vertices(d, N):
+    """Interior vertices, as arrays v[i] (direction i), x fastest ordering."""
+    out = []
+    for vv in itertools.product(range(1, N), repeat=d):
+        out.append(vv[::-1])
+    return np.array(out, dtype=np.int64).reshape(-1, d)
+
+
+def colour(v):
+    return int(sum(((v[i] - 1) % 2) << i for i in range(len(v))))
+
+
+def kept_1d(k, N, vi):
+    """Kept patch-local 1-D indices of the Dirichlet space along one direction."""
+    keep = list(range(1, 2 * k + 1))
+    if vi == 1:
+        keep = [0] + keep
+    if vi == N - 1:
+        keep = keep + [2 * k + 1]
+    return keep
+
+
+def patch_type_1d(N, vi):
+    """0 interior, 1 touches x=0, 2 touches x=1, 3 both (only N = 2)."""
+    return int(vi == 1) + 2 * int(vi == N - 1)
+
+
+def patch_dofs(d, k, N, v):
+    """Global (cell-wise) DoF index of every patch-tile node, as an array of
+    shape (2n,)*d indexed [p_{d-1}, ..., p_0]."""
+    n = k + 1
+    nl = n ** d
+    E = 2 * n
+    idx = np.zeros((E,) * d, dtype=np.int64)
+    for pt in itertools.product(range(E), repeat=d):
+        p = pt[::-1]
+        c = [v[i] - 1 + p[i] // n for i in range(d)]
+        l = [p[i] % n for i in range(d)]
+        cell = sum(c[i] * N ** i for i in range(d))
+        loc = sum(l[i] * n ** i for i in range(d))
+        idx[pt] = cell * nl + loc
+    return idx
+
+
+def kept_mask(d, k, N, v):
+    """Boolean mask over the patch tile (indexed [p_{d-1},...,p_0]) of V_j."""
+    E = 2 * (k + 1)
+    m = np.ones((E,) * d, dtype=bool)
+    for i in range(d):
+        keep = np.zeros(E, dtype=bool)
+        keep[kept_1d(k, N, v[i])] = True
+        shape = [1] * d
+        shape[d - 1 - i] = E
+        m &= keep.reshape(shape)
+    return m
+
+
+class PatchSet:
+    """All interior-vertex patches of a level with their tiles and colours."""
+
+    def __init__(self, d, k, N):
+        self.d, self.k, self.N = d, k, N
+        self.verts = vertices(d, N)
+        self.colours = np.array([colour(v) for v in self.verts], dtype=np.int64)
+        self.tiles = np.stack([patch_dofs(d, k, N, v) for v in self.verts])
+        self.masks = np.stack([kept_mask(d, k, N, v) for v in self.verts])
+
+    def of_colour(self, c):
+        return np.nonzero(self.colours == c)[0]
+
+    def vj(self, j):
+        """Global DoF indices of V_j (in tile order)."""
+        return self.tiles[j][self.masks[j]]
+
+    def vbar(self, j):
+        return self.tiles[j].reshape(-1)

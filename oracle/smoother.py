@@ -1,0 +1,191 @@
+"""Oracle (test infrastructure only): one step of the colourised
+multiplicative vertex-patch Schwarz smoother S(x, b) of Alg. 1 (Sec. 3.1),
+with local solves by fast diagonalisation (Sec. 3.2, eqs. inverse2d,
+inverse3d, fast_inverse).
+
+For every colour in the given order, and every patch j of that colour:
+    r_j = local residual on V_j
+    x|V_j += A[V_j, V_j]^{-1} r_j
+Two readings of the local residual:
+  'exact'  r_j = (b - A x)|V_j, the residual of eq. (residual) restricted to V_j;
+  'local'  r_j = b|V_j - A[V_j, Vbar_j] x|Vbar_j, the paper-literal Dirichlet
+           kernel that only sees the patch cells (inconsistent by design).
+Both use the global matrix entries restricted to the index sets.
+
+`smooth_dense` is the definition itself: patches visited one after another,
+residual rows taken from the assembled sparse matrix, dense local solves.
+`smooth_fd` processes one colour at a time (same-colour patches share no
+cell and no patch reads another same-colour write set, so this equals the
+sequential order) and inverts A[V_j,V_j] = sum_i (x) (M~ .. L~_i .. M~) by
+fast diagonalisation: L~ S = M~ S Lambda, S^T M~ S = I,
+A_j^{-1} = ((x) S) (sum_i Lambda_i)^{-1} ((x) S^T).
+"""
+import itertools
+
+import numpy as np
+import scipy.linalg as sla
+
+from .patches import PatchSet, kept_1d, patch_type_1d
+from .sipg import KronApply, sipg_1d
+
+
+def smooth_dense(A, x, b, ps, order, mode="exact"):
+    """Sequential by-definition smoothing step (in place on a copy of x)."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    A = A.tocsr()
+    for c in order:
+        for j in ps.of_colour(c):
+            V = ps.vj(j)
+            if mode == "exact":
+                r = b[V] - A[V] @ x
+            elif mode == "local":
+                Vb = ps.vbar(j)
+                r = b[V] - A[V][:, Vb] @ x[Vb]
+            else:
+                raise ValueError(mode)
+            Ajj = A[V][:, V].toarray()
+            x[V] += np.linalg.solve(Ajj, r)
+    return x
+
+
+class PatchFD:
+    """1-D patch matrices and their generalised eigenpairs for every patch
+    type along one direction (interior, touching x=0, touching x=1, both)."""
+
+    def __init__(self, k, N, sigma, kappa=1.0):
+        M, L = sipg_1d(k, N, sigma)
+        L = kappa * L
+        n = k + 1
+        self.k, self.N = k, N
+        self.S, self.lam, self.Mt, self.Lt, self.keep = {}, {}, {}, {}, {}
+        self.Mpatch, self.Lpatch = {}, {}
+        for vi in range(1, N):
+            t = patch_type_1d(N, vi)
+            if t in self.S:
+                continue
+            s = slice((vi - 1) * n, (vi + 1) * n)
+            Mp, Lp = M[s, s], L[s, s]
+            keep = kept_1d(k, N, vi)
+            Mt, Lt = Mp[np.ix_(keep, keep)], Lp[np.ix_(keep, keep)]
+            lam, S = sla.eigh(Lt, Mt)
+            self.S[t], self.lam[t] = S, lam
+            self.Mt[t], self.Lt[t], self.keep[t] = Mt, Lt, keep
+            self.Mpatch[t], self.Lpatch[t] = Mp, Lp
+
+
+def _along(A1, T, axis):
+    """Contract the 1-D matrix A1 (rows out, cols in) along tile axis `axis` of a
+    batch of tiles T (axis 0 is the patch batch)."""
+    Tm = np.moveaxis(T, axis, -1)
+    Y = Tm @ A1.T
+    return np.moveaxis(Y, -1, axis)
+
+
+def fd_inverse(fd, types, R):
+    """Apply A_j^{-1} by fast diagonalisation to a batch of kept-set tiles R
+    (shape (np, n_{d-1}, ..., n_0)) of patches sharing the type tuple `types`
+    (types[i] = type along direction i)."""
+    d = len(types)
+    T = R
+    for i in range(d):
+        T = _along(fd.S[types[i]].T, T, d - i)
+    lam = np.zeros(T.shape[1:])
+    for i in range(d):
+        shape = [1] * d
+        shape[d - 1 - i] = -1
+        lam = lam + fd.lam[types[i]].reshape(shape)
+    T = T / lam[None]
+    for i in range(d):
+        T = _along(fd.S[types[i]], T, d - i)
+    return T
+
+
+class FDSmoother:
+    """Vectorised smoothing step for one level (cell-wise layout)."""
+
+    def __init__(self, d, k, N, sigma, kappa=1.0, mode="exact", apply=None):
+        self.d, self.k, self.N, self.mode = d, k, N, mode
+        self.ps = PatchSet(d, k, N)
+        self.fd = PatchFD(k, N, sigma, kappa)
+        self.apply = apply if apply is not None else KronApply(d, k, N, sigma, kappa)
+        # group patches by (colour, type tuple)
+        self.groups = {}
+        for j, v in enumerate(self.ps.verts):
+            types = tuple(patch_type_1d(N, v[i]) for i in range(d))
+            self.groups.setdefault((int(self.ps.colours[j]), types), []).append(j)
+        self.groups = {key: np.array(val) for key, val in self.groups.items()}
+
+    def _kept_slices(self, types):
+        return tuple(np.array(self.fd.keep[types[i]]) for i in reversed(range(self.d)))
+
+    def step(self, x, b, order):
+        d = self.d
+        x = np.array(x, dtype=np.float64, copy=True)
+        for c in order:
+            r = b - self.apply(x) if self.mode == "exact" else None
+            updates = []
+            for (cc, types), js in self.groups.items():
+                if cc != c:
+                    continue
+                tiles = self.ps.tiles[js]  # (np, E,...,E)
+                ks = self._kept_slices(types)
+                sub = tiles[(slice(None),) + np.ix_(*ks)]
+                if self.mode == "exact":
+                    R = r[sub]
+                else:
+                    X = x[tiles]
+                    AX = np.zeros_like(X)
+                    for dirn in range(d):
+                        T = X
+                        for i in range(d):
+                            mat = self.fd.Lpatch[types[i]] if i == dirn else self.fd.Mpatch[types[i]]
+                            T = _along(mat, T, d - i)
+                        AX += T
+                    R = b[sub] - AX[(slice(None),) + np.ix_(*ks)]
+                updates.append((sub, fd_inverse(self.fd, types, R)))
+            for sub, dx in updates:
+                x[sub] += dx
+        return x
+
+
+def colour_orders(d):
+    asc = list(range(2 ** d))
+    return asc, asc[::-1]
+
+
+def colour_disjointness(ps):
+    """Race-freedom of one colour: write sets pairwise disjoint, and no patch
+    reads (tile plus the face-neighbour nodes the exact residual needs) another
+    same-colour patch's write set.  Returns True when every colour passes."""
+    d, k, N = ps.d, ps.k, ps.N
+    n = k + 1
+    nl = n ** d
+    for c in range(2 ** d):
+        js = ps.of_colour(c)
+        owner = {}
+        for j in js:
+            for g in ps.vj(j):
+                if g in owner:
+                    return False
+                owner[int(g)] = j
+        for j in js:
+            reads = set(int(g) for g in ps.vbar(j))
+            v = ps.verts[j]
+            # trace nodes of face-neighbour cells across the patch boundary
+            for i in range(d):
+                for side in (-1, 1):
+                    ci = v[i] - 2 if side < 0 else v[i] + 1
+                    if ci < 0 or ci >= N:
+                        continue
+                    for rest in itertools.product(*[(v[m] - 1, v[m]) for m in range(d) if m != i]):
+                        cc = list(rest)
+                        cc.insert(i, ci)
+                        cell = sum(cc[m] * N ** m for m in range(d))
+                        for loc in range(nl):
+                            li = (loc // n ** i) % n
+                            if li == (n - 1 if side < 0 else 0):
+                                reads.add(cell * nl + loc)
+            for g in reads:
+                if g in owner and owner[g] != j:
+                    return False
+    return True

@@ -1,0 +1,172 @@
+"""Pins of the oracle's smoother, V-cycle, Krylov solvers and adjoint
+(Alg. 1, Sec. 3, Sec. 3.2, Sec. 3.3) against definitions, invariants and the
+paper's printed iteration counts."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.adjoint import closed_form_dkappa, dense_adjoint
+from oracle.fdsolve import GlobalFD
+from oracle.multigrid import Hierarchy, fractional_iterations, gmres, pcg
+from oracle.patches import PatchSet
+from oracle.rhs import load_vector, sine_load
+from oracle.sipg import kron_operator
+from oracle.smoother import FDSmoother, colour_orders, smooth_dense
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def sig(k):
+    return 2.0 * (k + 1) ** 2
+
+
+@pytest.mark.parametrize("d,k,N", [(2, 1, 4), (2, 2, 4), (2, 3, 5), (3, 1, 4), (3, 2, 3)])
+@pytest.mark.parametrize("mode", ["exact", "local"])
+def test_fd_smoother_equals_sequential_dense_definition(d, k, N, mode):
+    A = kron_operator(d, k, N, sig(k), kappa=1.5)
+    ps = PatchSet(d, k, N)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(A.shape[0])
+    b = rng.standard_normal(A.shape[0])
+    asc, desc = colour_orders(d)
+    for order in (asc, desc):
+        x1 = smooth_dense(A, x, b, ps, order, mode)
+        x2 = FDSmoother(d, k, N, sig(k), kappa=1.5, mode=mode).step(x, b, order)
+        assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x1)
+
+
+def test_exact_smoother_fixed_point_is_solution():
+    d, k, N = 2, 2, 4
+    A = kron_operator(d, k, N, sig(k))
+    b = np.random.default_rng(0).standard_normal(A.shape[0])
+    u = GlobalFD(d, k, N, sig(k)).solve(b)
+    x = FDSmoother(d, k, N, sig(k), mode="exact").step(u, b, list(range(4)))
+    assert np.linalg.norm(x - u) <= 1e-12 * np.linalg.norm(u)
+    # the paper-literal kernel ignores the coupling to outside traces
+    xl = FDSmoother(d, k, N, sig(k), mode="local").step(u, b, list(range(4)))
+    assert np.linalg.norm(xl - u) > 1e-6 * np.linalg.norm(u)
+
+
+def _vcycle_matrix(H):
+    n = H.ndofs(H.L)
+    return np.stack([H.vcycle(e) for e in np.eye(n)], axis=1)
+
+
+@pytest.mark.parametrize("d,k,L", [(2, 1, 2), (2, 2, 2), (3, 1, 1)])
+def test_vcycle_symmetric_positive_definite(d, k, L):
+    B = _vcycle_matrix(Hierarchy(d, k, L, sig(k), mode="exact"))
+    assert np.abs(B - B.T).max() <= 1e-13 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T))[0] > 0
+
+
+def test_paper_literal_vcycle_is_not_symmetric():
+    B = _vcycle_matrix(Hierarchy(2, 2, 2, sig(2), mode="local"))
+    assert np.abs(B - B.T).max() > 1e-3 * np.abs(B).max()
+
+
+def test_fd_vcycle_equals_dense_vcycle():
+    d, k, L = 2, 2, 2
+    e = np.random.default_rng(2).standard_normal(Hierarchy(d, k, L, sig(k)).ndofs(L))
+    v1 = Hierarchy(d, k, L, sig(k), dense=True).vcycle(e)
+    v2 = Hierarchy(d, k, L, sig(k), dense=False).vcycle(e)
+    assert np.linalg.norm(v1 - v2) <= 1e-12 * np.linalg.norm(v1)
+
+
+def test_two_level_on_coarsest_is_exact():
+    # L = 0: the V-cycle is the exact coarse solve
+    d, k = 2, 3
+    H = Hierarchy(d, k, 0, sig(k))
+    A0 = kron_operator(d, k, 2, sig(k))
+    b = np.random.default_rng(1).standard_normal(A0.shape[0])
+    assert np.linalg.norm(A0 @ H.vcycle(b) - b) <= 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("d,k", [(2, 2), (2, 4)])
+def test_pcg_robust_in_h(d, k):
+    its = []
+    for L in (1, 2, 3, 4):
+        H = Hierarchy(d, k, L, sig(k))
+        b = load_vector(d, k, H.N[L], sine_load)
+        x, it, hist, true_rel = pcg(H.apply[L], H.vcycle, b, rtol=1e-10)
+        assert true_rel <= 2e-10
+        u = GlobalFD(d, k, H.N[L], sig(k)).solve(b)
+        assert np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u)
+        its.append(it)
+    assert max(its) - min(its) <= 2, its
+    assert max(its) <= 10
+
+
+def test_pcg_robust_in_k():
+    its = {}
+    for k in (2, 3, 4, 5, 6):
+        H = Hierarchy(2, k, 3, sig(k))
+        b = load_vector(2, k, H.N[3], sine_load)
+        its[k] = pcg(H.apply[3], H.vcycle, b, rtol=1e-10)[1]
+    assert its[6] <= its[2] + 1, its
+
+
+def test_flexible_beta_equals_standard_in_fp64():
+    H = Hierarchy(2, 3, 3, sig(3))
+    b = load_vector(2, 3, H.N[3], sine_load)
+    x1, i1, h1, _ = pcg(H.apply[3], H.vcycle, b, rtol=1e-10)
+    x2, i2, h2, _ = pcg(H.apply[3], H.vcycle, b, rtol=1e-10, flexible=True)
+    assert i1 == i2
+    assert np.linalg.norm(x1 - x2) <= 1e-9 * np.linalg.norm(x1)
+
+
+def test_fp32_vcycle_inside_fp64_cg_reaches_1e10():
+    H = Hierarchy(2, 3, 3, sig(3), dtype=np.float32)
+    b = load_vector(2, 3, H.N[3], sine_load)
+    x, it, hist, true_rel = pcg(H.apply[3], H.vcycle, b, rtol=1e-10, flexible=True)
+    assert true_rel <= 2e-10 and it <= 12
+
+
+def _golden_nu():
+    rows = []
+    with open(os.path.join(GOLDEN, "table2_dirichlet_nu.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                L, k, nu = line.split()
+                rows.append((int(L), int(k), float(nu)))
+    return rows
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("k", [3, 4])
+def test_gmres_nu_weak_pin_table2(k):
+    """nu of GMRES(1e-8, f = 1, 3-D, L = 2) with the consistent Dirichlet kernel
+    and the paper's penalty lies within 1.5 of Table 2 (Dirichlet kernel)."""
+    ref = {(L, kk): nu for L, kk, nu in _golden_nu()}[(2, k)]
+    H = Hierarchy(3, k, 2, 2.0 * k * (k + 1), mode="exact")
+    b = load_vector(3, k, H.N[2], lambda X: np.ones(X.shape[0]))
+    _, m, hist = gmres(H.apply[2], H.vcycle, b, rtol=1e-8)
+    nu = fractional_iterations(hist)
+    assert abs(nu - ref) <= 1.5, (nu, ref)
+
+
+def test_nu_formula_counts_steps():
+    # a constant reduction rate of 1e-4 per step needs nu = 2 steps per 8 digits
+    hist = [1.0, 1e-4, 1e-8, 1e-12]
+    assert abs(fractional_iterations(hist) - 2.0) < 1e-12
+
+
+def test_adjoint_dense_and_closed_form_and_fd():
+    d, k, N = 2, 2, 4
+    A1 = kron_operator(d, k, N, sig(k))
+    rng = np.random.default_rng(9)
+    b = rng.standard_normal(A1.shape[0])
+    ut = rng.standard_normal(A1.shape[0]) * 0.01
+    kappa = 1.3
+    u, loss, lam, dk = dense_adjoint(A1, kappa, b, ut)
+    assert abs(dk - closed_form_dkappa(u, ut, kappa)) <= 1e-10 * abs(dk)
+    eps = 1e-6
+    lp = dense_adjoint(A1, kappa + eps, b, ut)[1]
+    lm = dense_adjoint(A1, kappa - eps, b, ut)[1]
+    assert abs((lp - lm) / (2 * eps) - dk) <= 1e-6 * abs(dk)
+    j = 7
+    e = np.zeros_like(b)
+    e[j] = eps
+    lp = dense_adjoint(A1, kappa, b + e, ut)[1]
+    lm = dense_adjoint(A1, kappa, b - e, ut)[1]
+    assert abs((lp - lm) / (2 * eps) - lam[j]) <= 1e-6 * np.abs(lam).max()
