@@ -80,15 +80,49 @@ def kept_mask(d, k, N, v):
     return m
 
 
+def _tiles_vectorised(d, k, N, verts):
+    """Global DoF indices of every patch tile, shape (P, 2n, ..., 2n) indexed
+    [patch, p_{d-1}, ..., p_0] (the same index rule as `patch_dofs`)."""
+    n = k + 1
+    E = 2 * n
+    P = len(verts)
+    p = np.arange(E)
+    cell = np.zeros((P,) + (1,) * d, dtype=np.int64)
+    loc = np.zeros((1,) + (1,) * d, dtype=np.int64)
+    for i in range(d):
+        shape = [1] * (d + 1)
+        shape[d - i] = E
+        ci = (verts[:, i][:, None] - 1 + (p // n)[None, :])
+        cell = cell + ci.reshape([P] + shape[1:]) * N ** i
+        loc = loc + (p % n).reshape(shape) * n ** i
+    return cell * n ** d + loc
+
+
+def _masks_vectorised(d, k, N, verts):
+    E = 2 * (k + 1)
+    P = len(verts)
+    m = np.ones((P,) + (E,) * d, dtype=bool)
+    p = np.arange(E)
+    for i in range(d):
+        vi = verts[:, i][:, None]
+        keep = ((p[None, :] >= 1) | (vi == 1)) & ((p[None, :] <= 2 * k) | (vi == N - 1))
+        shape = [P] + [1] * d
+        shape[d - i] = E
+        m &= keep.reshape(shape)
+    return m
+
+
 class PatchSet:
     """All interior-vertex patches of a level with their tiles and colours."""
 
     def __init__(self, d, k, N):
         self.d, self.k, self.N = d, k, N
         self.verts = vertices(d, N)
-        self.colours = np.array([colour(v) for v in self.verts], dtype=np.int64)
-        self.tiles = np.stack([patch_dofs(d, k, N, v) for v in self.verts])
-        self.masks = np.stack([kept_mask(d, k, N, v) for v in self.verts])
+        self.colours = np.zeros(len(self.verts), dtype=np.int64)
+        for i in range(d):
+            self.colours += ((self.verts[:, i] - 1) % 2) << i
+        self.tiles = _tiles_vectorised(d, k, N, self.verts)
+        self.masks = _masks_vectorised(d, k, N, self.verts)
 
     def of_colour(self, c):
         return np.nonzero(self.colours == c)[0]

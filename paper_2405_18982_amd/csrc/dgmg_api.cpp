@@ -1,0 +1,669 @@
+// C ABI of libdgmg.so (declared in include/dgmg.h): context, level
+// hierarchy, host-orchestrated V-cycle and preconditioned CG.
+//
+// The V-cycle follows Sec. 3 with one kernel per operation, issued from the
+// host in order on one stream (the paper's compute layout, Sec. 4.2):
+//   level l = L .. 1: smooth (2^d colour launches), residual + restriction
+//   level 0:          exact coarse solve
+//   level l = 1 .. L: prolongation + add, smooth (colours reversed)
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dgmg.h"
+#include "dgmg_blas.h"
+#include "dgmg_internal.h"
+#include "dgmg_setup.h"
+
+#define DGMG_API extern "C" __attribute__((visibility("default")))
+
+DGMG_DECLARE_ENTRY(2, 1)
+DGMG_DECLARE_ENTRY(2, 2)
+DGMG_DECLARE_ENTRY(2, 3)
+DGMG_DECLARE_ENTRY(2, 4)
+DGMG_DECLARE_ENTRY(2, 5)
+DGMG_DECLARE_ENTRY(2, 6)
+DGMG_DECLARE_ENTRY(2, 7)
+DGMG_DECLARE_ENTRY(3, 1)
+DGMG_DECLARE_ENTRY(3, 2)
+DGMG_DECLARE_ENTRY(3, 3)
+DGMG_DECLARE_ENTRY(3, 4)
+DGMG_DECLARE_ENTRY(3, 5)
+DGMG_DECLARE_ENTRY(3, 6)
+DGMG_DECLARE_ENTRY(3, 7)
+
+namespace {
+
+using dgmg::KernelEntry;
+using dgmg::KernelSet;
+using dgmg::PatchGrid;
+
+const KernelEntry* kernels_for(int dim, int k) {
+  static KernelEntry table[2][dgmg::kMaxDegree];
+  static bool init = false;
+  if (!init) {
+    void (*f2[])(KernelEntry*) = {dgmg_kernels_d2_k1, dgmg_kernels_d2_k2, dgmg_kernels_d2_k3,
+                                  dgmg_kernels_d2_k4, dgmg_kernels_d2_k5, dgmg_kernels_d2_k6,
+                                  dgmg_kernels_d2_k7};
+    void (*f3[])(KernelEntry*) = {dgmg_kernels_d3_k1, dgmg_kernels_d3_k2, dgmg_kernels_d3_k3,
+                                  dgmg_kernels_d3_k4, dgmg_kernels_d3_k5, dgmg_kernels_d3_k6,
+                                  dgmg_kernels_d3_k7};
+    for (int i = 0; i < dgmg::kMaxDegree; ++i) {
+      f2[i](&table[0][i]);
+      f3[i](&table[1][i]);
+    }
+    init = true;
+  }
+  return &table[dim - 2][k - 1];
+}
+
+struct Level {
+  int N = 0;
+  long long ndof = 0;
+  double h = 0;
+  double* b64 = nullptr;
+  double* x64 = nullptr;
+  float* b32 = nullptr;
+  float* x32 = nullptr;
+};
+
+template <int K, typename T>
+void fill_tab(const dgmg::HostTables& H, std::vector<unsigned char>& out) {
+  using Tb = dgmg::Tab<K, T>;
+  out.assign(sizeof(Tb), 0);
+  Tb* t = reinterpret_cast<Tb*>(out.data());
+  constexpr int n = K + 1, E = 2 * n;
+  for (int i = 0; i < n * n; ++i) {
+    t->M[i] = (T)H.M[i];
+    t->Lc[i] = (T)H.Lc[i];
+  }
+  for (int i = 0; i < n; ++i) {
+    t->d0[i] = (T)H.d0[i];
+    t->d1[i] = (T)H.d1[i];
+  }
+  t->sigma = (T)H.sigma;
+  for (int ty = 0; ty < 4; ++ty) {
+    for (int i = 0; i < E * E; ++i) t->S[ty][i] = (T)H.S[ty][i];
+    for (int i = 0; i < E; ++i) t->lam[ty][i] = (T)H.lam[ty][i];
+  }
+  for (int i = 0; i < E * n; ++i) t->P[i] = (T)H.P[i];
+}
+
+template <typename T>
+void fill_tab_k(int k, const dgmg::HostTables& H, std::vector<unsigned char>& out) {
+  switch (k) {
+    case 1: fill_tab<1, T>(H, out); break;
+    case 2: fill_tab<2, T>(H, out); break;
+    case 3: fill_tab<3, T>(H, out); break;
+    case 4: fill_tab<4, T>(H, out); break;
+    case 5: fill_tab<5, T>(H, out); break;
+    case 6: fill_tab<6, T>(H, out); break;
+    default: fill_tab<7, T>(H, out); break;
+  }
+}
+
+}  // namespace
+
+struct dgmg_ctx {
+  int dim = 0, k = 0, L = 0;
+  double sigma = 0, kappa = 1;
+  dgmg::HostTables host;
+  const KernelEntry* ks = nullptr;
+  std::vector<Level> lv;
+  bool ready = false;
+  int prec = 64, variant = 0, nrhs_max = 1;
+  hipStream_t stream = nullptr;
+  void* tab64 = nullptr;
+  void* tab32 = nullptr;
+  // Krylov workspace (finest level, FP64) and scalars
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double* scal = nullptr;  // kNumScal arrays of nrhs_max
+  double *partial = nullptr, *partial2 = nullptr;
+  int* active = nullptr;
+  double* hbuf = nullptr;  // pinned host mirror of scalars
+  int* hact = nullptr;
+  std::string err;
+};
+
+namespace {
+
+enum { S_BB = 0, S_RR, S_PQ, S_ALPHA, S_RZ0, S_RZ1, S_ZQ, kNumScal };
+
+dgmg_status fail(dgmg_ctx* c, dgmg_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, DGMG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+T* dalloc(long long count, hipError_t& e) {
+  void* p = nullptr;
+  e = hipMalloc(&p, (size_t)count * sizeof(T));
+  return e == hipSuccess ? (T*)p : nullptr;
+}
+
+PatchGrid grid_colour0(const dgmg_ctx* c, int N) {
+  PatchGrid g{};
+  g.N = N;
+  g.npatch = 1;
+  for (int i = 0; i < 3; ++i) {
+    g.cnt[i] = (i < c->dim) ? N / 2 : 1;
+    g.off[i] = 0;
+    g.npatch *= g.cnt[i];
+  }
+  return g;
+}
+
+PatchGrid grid_colour(const dgmg_ctx* c, int N, int colour) {
+  PatchGrid g{};
+  g.N = N;
+  g.npatch = 1;
+  for (int i = 0; i < 3; ++i) {
+    if (i < c->dim) {
+      g.off[i] = (colour >> i) & 1;
+      g.cnt[i] = g.off[i] ? (N - 2) / 2 : N / 2;
+    } else {
+      g.off[i] = 0;
+      g.cnt[i] = 1;
+    }
+    g.npatch *= g.cnt[i];
+  }
+  return g;
+}
+
+double level_scale(const dgmg_ctx* c, int l) {
+  return c->kappa * std::pow(c->lv[l].h, c->dim - 2);
+}
+
+template <typename T>
+const KernelSet<T>& kset(const dgmg_ctx* c);
+template <>
+const KernelSet<double>& kset<double>(const dgmg_ctx* c) { return c->ks->f64; }
+template <>
+const KernelSet<float>& kset<float>(const dgmg_ctx* c) { return c->ks->f32; }
+template <typename T>
+void* tab_of(const dgmg_ctx* c) { return sizeof(T) == 8 ? c->tab64 : c->tab32; }
+
+dgmg_status check_ready(dgmg_ctx* c) {
+  if (!c) return DGMG_ERR_ARG;
+  if (!c->ready) return fail(c, DGMG_ERR_STATE, "dgmg_setup_levels has not been called");
+  return DGMG_OK;
+}
+
+dgmg_status check_level(dgmg_ctx* c, int level, int lo, int nrhs) {
+  dgmg_status s = check_ready(c);
+  if (s != DGMG_OK) return s;
+  if (level < lo || level > c->L) return fail(c, DGMG_ERR_ARG, "level out of range");
+  if (nrhs < 1 || nrhs > c->nrhs_max) return fail(c, DGMG_ERR_ARG, "nrhs out of range [1, nrhs_max]");
+  return DGMG_OK;
+}
+
+// ------------------------------------------------------------ level ops
+template <typename T>
+dgmg_status op_apply(dgmg_ctx* c, int l, const T* x, T* y, int nrhs) {
+  HIPCHK(c, kset<T>(c).apply(tab_of<T>(c), grid_colour0(c, c->lv[l].N), (T)level_scale(c, l), x, y,
+                             nrhs, c->lv[l].ndof, c->stream));
+  return DGMG_OK;
+}
+
+template <typename T>
+dgmg_status op_smooth(dgmg_ctx* c, int l, T* x, const T* b, int reverse, int nrhs) {
+  const double sc = level_scale(c, l);
+  const int nc = 1 << c->dim;
+  for (int i = 0; i < nc; ++i) {
+    const int col = reverse ? nc - 1 - i : i;
+    PatchGrid g = grid_colour(c, c->lv[l].N, col);
+    if (g.npatch == 0) continue;
+    HIPCHK(c, kset<T>(c).smooth(tab_of<T>(c), g, (T)sc, (T)(1.0 / sc), c->variant, x, b, nrhs,
+                                c->lv[l].ndof, c->stream));
+  }
+  return DGMG_OK;
+}
+
+template <typename T>
+dgmg_status op_restrict(dgmg_ctx* c, int l, const T* x, const T* b, T* bc, int nrhs) {
+  HIPCHK(c, kset<T>(c).restrict_residual(tab_of<T>(c), grid_colour0(c, c->lv[l].N),
+                                         (T)level_scale(c, l), x, b, bc, nrhs, c->lv[l].ndof,
+                                         c->lv[l - 1].ndof, c->stream));
+  return DGMG_OK;
+}
+
+template <typename T>
+dgmg_status op_prolong(dgmg_ctx* c, int l, const T* xc, T* x, int nrhs) {
+  HIPCHK(c, kset<T>(c).prolongate_add(tab_of<T>(c), grid_colour0(c, c->lv[l].N), xc, x, nrhs,
+                                      c->lv[l].ndof, c->lv[l - 1].ndof, c->stream));
+  return DGMG_OK;
+}
+
+template <typename T>
+dgmg_status op_coarse(dgmg_ctx* c, const T* b, T* x, int nrhs) {
+  HIPCHK(c, kset<T>(c).coarse(tab_of<T>(c), (T)(1.0 / level_scale(c, 0)), b, x, nrhs, c->lv[0].ndof,
+                              c->stream));
+  return DGMG_OK;
+}
+
+template <typename T>
+dgmg_status zero_vec(dgmg_ctx* c, T* a, long long n) {
+  if (sizeof(T) == 8) HIPCHK(c, dgmg::blas_zero_f64((double*)a, n, c->stream));
+  else HIPCHK(c, dgmg::blas_zero_f32((float*)a, n, c->stream));
+  return DGMG_OK;
+}
+
+template <typename T>
+T*& lvb(Level& L);
+template <>
+double*& lvb<double>(Level& L) { return L.b64; }
+template <>
+float*& lvb<float>(Level& L) { return L.b32; }
+template <typename T>
+T*& lvx(Level& L);
+template <>
+double*& lvx<double>(Level& L) { return L.x64; }
+template <>
+float*& lvx<float>(Level& L) { return L.x32; }
+
+// Library-owned level vectors of precision T on levels [0, upto].
+template <typename T>
+dgmg_status ensure_levels(dgmg_ctx* c, int upto) {
+  for (int l = 0; l <= upto; ++l) {
+    Level& L = c->lv[l];
+    hipError_t e = hipSuccess;
+    const long long cnt = L.ndof * c->nrhs_max;
+    if (!lvb<T>(L)) lvb<T>(L) = dalloc<T>(cnt, e);
+    if (e != hipSuccess) return fail(c, DGMG_ERR_ALLOC, "level vector allocation failed");
+    if (!lvx<T>(L)) lvx<T>(L) = dalloc<T>(cnt, e);
+    if (e != hipSuccess) return fail(c, DGMG_ERR_ALLOC, "level vector allocation failed");
+  }
+  return DGMG_OK;
+}
+
+#define RET(expr)                          \
+  do {                                     \
+    dgmg_status s_ = (expr);               \
+    if (s_ != DGMG_OK) return s_;          \
+  } while (0)
+
+// x = V(b) on level L with b, x given (may be caller or library buffers);
+// coarser levels use the library's vectors of precision T.
+template <typename T>
+dgmg_status vcycle_T(dgmg_ctx* c, const T* bL, T* xL, int nrhs) {
+  RET(ensure_levels<T>(c, c->L - 1));
+  const int L = c->L;
+  auto B = [&](int l) -> const T* { return l == L ? bL : lvb<T>(c->lv[l]); };
+  auto X = [&](int l) -> T* { return l == L ? xL : lvx<T>(c->lv[l]); };
+  for (int l = L; l >= 1; --l) {
+    RET(zero_vec<T>(c, X(l), c->lv[l].ndof * nrhs));
+    RET(op_smooth<T>(c, l, X(l), B(l), 0, nrhs));
+    RET(op_restrict<T>(c, l, X(l), B(l), lvb<T>(c->lv[l - 1]), nrhs));
+  }
+  RET(op_coarse<T>(c, B(0), X(0), nrhs));
+  for (int l = 1; l <= L; ++l) {
+    RET(op_prolong<T>(c, l, X(l - 1), X(l), nrhs));
+    RET(op_smooth<T>(c, l, X(l), B(l), 1, nrhs));
+  }
+  return DGMG_OK;
+}
+
+// z = V(r) in the context precision (FP64 vectors in and out).
+dgmg_status precondition(dgmg_ctx* c, const double* r, double* z, int nrhs) {
+  if (c->prec == 64) return vcycle_T<double>(c, r, z, nrhs);
+  RET(ensure_levels<float>(c, c->L));
+  Level& T = c->lv[c->L];
+  const long long n = T.ndof * nrhs;
+  HIPCHK(c, dgmg::blas_f64_to_f32(r, T.b32, n, c->stream));
+  RET(vcycle_T<float>(c, T.b32, T.x32, nrhs));
+  HIPCHK(c, dgmg::blas_f32_to_f64(T.x32, z, n, c->stream));
+  return DGMG_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+DGMG_API dgmg_status dgmg_setup_mesh(int dim, int degree, int finest_level, double penalty_sigma,
+                                     double kappa, dgmg_ctx** out) {
+  if (!out) return DGMG_ERR_ARG;
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return DGMG_ERR_ARG;
+  if (degree < 1 || degree > dgmg::kMaxDegree) return DGMG_ERR_ARG;
+  if (finest_level < 1 || finest_level > 20) return DGMG_ERR_ARG;
+  if (!(penalty_sigma > 0) || !std::isfinite(penalty_sigma)) return DGMG_ERR_ARG;
+  if (!(kappa > 0) || !std::isfinite(kappa)) return DGMG_ERR_ARG;
+  const double nd = std::pow(2.0, (finest_level + 1) * dim) * std::pow(degree + 1.0, dim);
+  if (nd >= std::pow(2.0, 40)) return DGMG_ERR_ARG;
+  dgmg_ctx* c = new (std::nothrow) dgmg_ctx;
+  if (!c) return DGMG_ERR_ALLOC;
+  c->dim = dim;
+  c->k = degree;
+  c->L = finest_level;
+  c->sigma = penalty_sigma;
+  c->kappa = kappa;
+  const char* err = nullptr;
+  if (!dgmg::build_host_tables(degree, penalty_sigma, c->host, &err)) {
+    delete c;
+    return DGMG_ERR_ARG;
+  }
+  c->lv.resize(finest_level + 1);
+  for (int l = 0; l <= finest_level; ++l) {
+    Level& L = c->lv[l];
+    L.N = 1 << (l + 1);
+    L.h = 1.0 / L.N;
+    L.ndof = 1;
+    for (int i = 0; i < dim; ++i) L.ndof *= (long long)L.N * (degree + 1);
+  }
+  c->ks = kernels_for(dim, degree);
+  *out = c;
+  return DGMG_OK;
+}
+
+DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int smoother_variant,
+                                       int nrhs_max, void* hip_stream) {
+  if (!c) return DGMG_ERR_ARG;
+  if (c->ready) return fail(c, DGMG_ERR_STATE, "levels already set up");
+  if (vcycle_precision != DGMG_FP64 && vcycle_precision != DGMG_FP32)
+    return fail(c, DGMG_ERR_ARG, "vcycle_precision must be 64 or 32");
+  if (smoother_variant != DGMG_SMOOTH_EXACT && smoother_variant != DGMG_SMOOTH_LOCAL)
+    return fail(c, DGMG_ERR_ARG, "unknown smoother variant");
+  if (nrhs_max < 1 || nrhs_max > 4096) return fail(c, DGMG_ERR_ARG, "nrhs_max out of range");
+  c->prec = vcycle_precision;
+  c->variant = smoother_variant;
+  c->nrhs_max = nrhs_max;
+  c->stream = (hipStream_t)hip_stream;
+  std::vector<unsigned char> t64, t32;
+  fill_tab_k<double>(c->k, c->host, t64);
+  fill_tab_k<float>(c->k, c->host, t32);
+  HIPCHK(c, hipMalloc(&c->tab64, t64.size()));
+  HIPCHK(c, hipMalloc(&c->tab32, t32.size()));
+  HIPCHK(c, hipMemcpy(c->tab64, t64.data(), t64.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->tab32, t32.data(), t32.size(), hipMemcpyHostToDevice));
+  const long long nL = c->lv[c->L].ndof * nrhs_max;
+  hipError_t e = hipSuccess;
+  c->r = dalloc<double>(nL, e);
+  if (e == hipSuccess) c->z = dalloc<double>(nL, e);
+  if (e == hipSuccess) c->p = dalloc<double>(nL, e);
+  if (e == hipSuccess) c->q = dalloc<double>(nL, e);
+  if (e == hipSuccess) c->scal = dalloc<double>((long long)kNumScal * nrhs_max, e);
+  if (e == hipSuccess) c->partial = dalloc<double>((long long)dgmg::kRedBlocks * nrhs_max, e);
+  if (e == hipSuccess) c->partial2 = dalloc<double>((long long)dgmg::kRedBlocks * nrhs_max, e);
+  if (e == hipSuccess) c->active = dalloc<int>(nrhs_max, e);
+  if (e != hipSuccess) return fail(c, DGMG_ERR_ALLOC, "workspace allocation failed");
+  HIPCHK(c, hipHostMalloc((void**)&c->hbuf, sizeof(double) * kNumScal * nrhs_max));
+  HIPCHK(c, hipHostMalloc((void**)&c->hact, sizeof(int) * nrhs_max));
+  c->ready = true;
+  if (vcycle_precision == DGMG_FP64) RET(ensure_levels<double>(c, c->L - 1));
+  else RET(ensure_levels<float>(c, c->L));
+  return DGMG_OK;
+}
+
+DGMG_API dgmg_status dgmg_set_stream(dgmg_ctx* c, void* hip_stream) {
+  if (!c) return DGMG_ERR_ARG;
+  c->stream = (hipStream_t)hip_stream;
+  return DGMG_OK;
+}
+
+DGMG_API dgmg_status dgmg_set_kappa(dgmg_ctx* c, double kappa) {
+  if (!c) return DGMG_ERR_ARG;
+  if (!(kappa > 0) || !std::isfinite(kappa)) return fail(c, DGMG_ERR_ARG, "kappa must be positive");
+  c->kappa = kappa;
+  return DGMG_OK;
+}
+
+DGMG_API long long dgmg_level_ndofs(const dgmg_ctx* c, int level) {
+  if (!c || level < 0 || level > c->L) return -1;
+  return c->lv[level].ndof;
+}
+
+DGMG_API int dgmg_level_cells(const dgmg_ctx* c, int level) {
+  if (!c || level < 0 || level > c->L) return -1;
+  return c->lv[level].N;
+}
+
+DGMG_API int dgmg_finest_level(const dgmg_ctx* c) { return c ? c->L : -1; }
+
+DGMG_API dgmg_status dgmg_node_coords(const dgmg_ctx* c, int level, double* xyz) {
+  if (!c || !xyz || level < 0 || level > c->L) return DGMG_ERR_ARG;
+  const int N = c->lv[level].N, n = c->k + 1, d = c->dim;
+  const double h = c->lv[level].h;
+  const long long ncell = (long long)std::pow((double)N, d);
+  const int nc = (int)std::pow((double)n, d);
+  long long idx = 0;
+  for (long long cell = 0; cell < ncell; ++cell) {
+    const long long cc[3] = {cell % N, (cell / N) % N, cell / ((long long)N * N)};
+    for (int loc = 0; loc < nc; ++loc) {
+      const int a[3] = {loc % n, (loc / n) % n, loc / (n * n)};
+      for (int i = 0; i < d; ++i) xyz[idx * d + i] = (cc[i] + c->host.nodes[a[i]]) * h;
+      ++idx;
+    }
+  }
+  return DGMG_OK;
+}
+
+DGMG_API dgmg_status dgmg_apply_sipg(dgmg_ctx* c, int level, const double* x, double* y, int nrhs) {
+  RET(check_level(c, level, 0, nrhs));
+  if (!x || !y) return fail(c, DGMG_ERR_ARG, "null vector");
+  return op_apply<double>(c, level, x, y, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_apply_sipg_f32(dgmg_ctx* c, int level, const float* x, float* y, int nrhs) {
+  RET(check_level(c, level, 0, nrhs));
+  if (!x || !y) return fail(c, DGMG_ERR_ARG, "null vector");
+  return op_apply<float>(c, level, x, y, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_apply_mass(dgmg_ctx* c, int level, const double* x, double* y, int nrhs) {
+  RET(check_level(c, level, 0, nrhs));
+  if (!x || !y) return fail(c, DGMG_ERR_ARG, "null vector");
+  const double sc = std::pow(c->lv[level].h, c->dim);
+  HIPCHK(c, c->ks->f64.mass(c->tab64, grid_colour0(c, c->lv[level].N), sc, x, y, nrhs,
+                            c->lv[level].ndof, c->stream));
+  return DGMG_OK;
+}
+
+DGMG_API dgmg_status dgmg_smooth_patch(dgmg_ctx* c, int level, double* x, const double* b,
+                                       int reverse_colours, int nrhs) {
+  RET(check_level(c, level, 1, nrhs));
+  if (!x || !b) return fail(c, DGMG_ERR_ARG, "null vector");
+  return op_smooth<double>(c, level, x, b, reverse_colours, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_smooth_patch_f32(dgmg_ctx* c, int level, float* x, const float* b,
+                                           int reverse_colours, int nrhs) {
+  RET(check_level(c, level, 1, nrhs));
+  if (!x || !b) return fail(c, DGMG_ERR_ARG, "null vector");
+  return op_smooth<float>(c, level, x, b, reverse_colours, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_restrict_residual(dgmg_ctx* c, int level, const double* x,
+                                            const double* b, double* bc, int nrhs) {
+  RET(check_level(c, level, 1, nrhs));
+  if (!x || !b || !bc) return fail(c, DGMG_ERR_ARG, "null vector");
+  return op_restrict<double>(c, level, x, b, bc, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_restrict_residual_f32(dgmg_ctx* c, int level, const float* x,
+                                                const float* b, float* bc, int nrhs) {
+  RET(check_level(c, level, 1, nrhs));
+  if (!x || !b || !bc) return fail(c, DGMG_ERR_ARG, "null vector");
+  return op_restrict<float>(c, level, x, b, bc, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_prolongate_add(dgmg_ctx* c, int level, const double* xc, double* x,
+                                         int nrhs) {
+  RET(check_level(c, level, 1, nrhs));
+  if (!x || !xc) return fail(c, DGMG_ERR_ARG, "null vector");
+  return op_prolong<double>(c, level, xc, x, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_prolongate_add_f32(dgmg_ctx* c, int level, const float* xc, float* x,
+                                             int nrhs) {
+  RET(check_level(c, level, 1, nrhs));
+  if (!x || !xc) return fail(c, DGMG_ERR_ARG, "null vector");
+  return op_prolong<float>(c, level, xc, x, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_coarse_solve(dgmg_ctx* c, const double* b, double* x, int nrhs) {
+  RET(check_level(c, 0, 0, nrhs));
+  if (!x || !b) return fail(c, DGMG_ERR_ARG, "null vector");
+  return op_coarse<double>(c, b, x, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_coarse_solve_f32(dgmg_ctx* c, const float* b, float* x, int nrhs) {
+  RET(check_level(c, 0, 0, nrhs));
+  if (!x || !b) return fail(c, DGMG_ERR_ARG, "null vector");
+  return op_coarse<float>(c, b, x, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_vcycle(dgmg_ctx* c, const double* b, double* x, int nrhs) {
+  RET(check_level(c, c ? c->L : 0, 0, nrhs));
+  if (!x || !b) return fail(c, DGMG_ERR_ARG, "null vector");
+  return precondition(c, b, x, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_vcycle_f32(dgmg_ctx* c, const float* b, float* x, int nrhs) {
+  RET(check_level(c, c ? c->L : 0, 0, nrhs));
+  if (!x || !b) return fail(c, DGMG_ERR_ARG, "null vector");
+  return vcycle_T<float>(c, b, x, nrhs);
+}
+
+DGMG_API dgmg_status dgmg_pcg_solve(dgmg_ctx* c, const double* b, double* x, int use_initial_guess,
+                                    double rtol, int maxit, int nrhs, int* iters, double* relres) {
+  RET(check_level(c, c ? c->L : 0, 0, nrhs));
+  if (!x || !b || !iters || !relres) return fail(c, DGMG_ERR_ARG, "null argument");
+  if (!(rtol > 0) || maxit < 1) return fail(c, DGMG_ERR_ARG, "rtol must be > 0 and maxit >= 1");
+  const long long n = c->lv[c->L].ndof;
+  hipStream_t s = c->stream;
+  const int R = c->nrhs_max;
+  double* bb = c->scal + S_BB * R;
+  double* rr = c->scal + S_RR * R;
+  double* pq = c->scal + S_PQ * R;
+  double* alpha = c->scal + S_ALPHA * R;
+  double* rzb[2] = {c->scal + S_RZ0 * R, c->scal + S_RZ1 * R};
+  double* zq = c->scal + S_ZQ * R;
+  const int flexible = (c->prec == 32);
+  // r = b - A x (or b), |b|^2
+  if (use_initial_guess) {
+    RET(op_apply<double>(c, c->L, x, c->q, nrhs));
+    HIPCHK(c, dgmg::blas_sub(b, c->q, c->r, n * nrhs, s));
+  } else {
+    RET(zero_vec<double>(c, x, n * nrhs));
+    HIPCHK(c, hipMemcpyAsync(c->r, b, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(c, dgmg::blas_dot2(b, b, c->r, c->r, n, nrhs, c->partial, c->partial2, bb, rr, s));
+  HIPCHK(c, hipMemcpyAsync(c->hbuf, c->scal, sizeof(double) * 2 * R, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  std::vector<double> nb(nrhs);
+  bool any = false;
+  for (int j = 0; j < nrhs; ++j) {
+    const double b2 = c->hbuf[S_BB * R + j], r2 = c->hbuf[S_RR * R + j];
+    if (!std::isfinite(b2) || !std::isfinite(r2))
+      return fail(c, DGMG_ERR_ARG, "right-hand side or initial guess contains NaN/Inf");
+    nb[j] = std::sqrt(b2);
+    iters[j] = 0;
+    relres[j] = (b2 > 0) ? std::sqrt(r2) / nb[j] : 0.0;
+    c->hact[j] = (b2 > 0 && relres[j] > rtol) ? 1 : 0;
+    any = any || c->hact[j];
+  }
+  if (!any) return DGMG_OK;
+  HIPCHK(c, hipMemcpyAsync(c->active, c->hact, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+  RET(precondition(c, c->r, c->z, nrhs));
+  HIPCHK(c, dgmg::blas_dot2(c->r, c->z, nullptr, nullptr, n, nrhs, c->partial, nullptr, rzb[0],
+                            nullptr, s));
+  HIPCHK(c, hipMemcpyAsync(c->p, c->z, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, s));
+  dgmg_status status = DGMG_ERR_NOT_CONVERGED;
+  for (int it = 1; it <= maxit; ++it) {
+    double* rz_old = rzb[(it - 1) & 1];
+    double* rz_new = rzb[it & 1];
+    RET(op_apply<double>(c, c->L, c->p, c->q, nrhs));
+    HIPCHK(c, dgmg::blas_dot2(c->p, c->q, nullptr, nullptr, n, nrhs, c->partial, nullptr, pq,
+                              nullptr, s));
+    HIPCHK(c, dgmg::blas_update_xr(x, c->r, c->p, c->q, rz_old, pq, c->active, n, nrhs, alpha,
+                                   c->partial, rr, s));
+    HIPCHK(c, hipMemcpyAsync(c->hbuf + S_RR * R, rr, sizeof(double) * 2 * R, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    any = false;
+    for (int j = 0; j < nrhs; ++j) {
+      if (!c->hact[j]) continue;
+      const double p2 = c->hbuf[S_PQ * R + j], r2 = c->hbuf[S_RR * R + j];
+      if (!(p2 > 0) || !std::isfinite(p2) || !std::isfinite(r2))
+        return fail(c, DGMG_ERR_BREAKDOWN, "CG breakdown: p^T A p <= 0 or non-finite scalar");
+      iters[j] = it;
+      relres[j] = std::sqrt(r2) / nb[j];
+      if (relres[j] <= rtol) c->hact[j] = 0;
+      any = any || c->hact[j];
+    }
+    if (!any) { status = DGMG_OK; break; }
+    HIPCHK(c, hipMemcpyAsync(c->active, c->hact, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    RET(precondition(c, c->r, c->z, nrhs));
+    HIPCHK(c, dgmg::blas_dot2(c->r, c->z, flexible ? c->z : nullptr, flexible ? c->q : nullptr, n,
+                              nrhs, c->partial, c->partial2, rz_new, zq, s));
+    HIPCHK(c, dgmg::blas_update_p(c->p, c->z, rz_new, rz_old, zq, alpha, c->active, flexible, n,
+                                  nrhs, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (status != DGMG_OK) c->err = "maximum number of iterations reached";
+  return status;
+}
+
+DGMG_API dgmg_status dgmg_dot(dgmg_ctx* c, int level, const double* a, const double* b, int nrhs,
+                              double* out) {
+  RET(check_level(c, level, 0, nrhs));
+  if (!a || !b || !out) return fail(c, DGMG_ERR_ARG, "null argument");
+  double* res = c->scal + S_ZQ * c->nrhs_max;
+  HIPCHK(c, dgmg::blas_dot2(a, b, nullptr, nullptr, c->lv[level].ndof, nrhs, c->partial, nullptr,
+                            res, nullptr, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->hbuf, res, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memcpy(out, c->hbuf, sizeof(double) * nrhs);
+  return DGMG_OK;
+}
+
+DGMG_API dgmg_status dgmg_patch_eigen(int degree, double sigma, int type, double* S, double* lam) {
+  if (degree < 1 || degree > dgmg::kMaxDegree || !(sigma > 0) || type < 0 || type > 3 || !S || !lam)
+    return DGMG_ERR_ARG;
+  dgmg::HostTables H;
+  const char* err = nullptr;
+  if (!dgmg::build_host_tables(degree, sigma, H, &err)) return DGMG_ERR_ARG;
+  std::memcpy(S, H.S[type].data(), sizeof(double) * H.E * H.E);
+  std::memcpy(lam, H.lam[type].data(), sizeof(double) * H.E);
+  return DGMG_OK;
+}
+
+DGMG_API const char* dgmg_last_error(const dgmg_ctx* c) {
+  return c ? c->err.c_str() : "null context";
+}
+
+DGMG_API dgmg_status dgmg_destroy(dgmg_ctx* c) {
+  if (!c) return DGMG_ERR_ARG;
+  if (c->ready) hipStreamSynchronize(c->stream);
+  for (Level& L : c->lv) {
+    hipFree(L.b64);
+    hipFree(L.x64);
+    hipFree(L.b32);
+    hipFree(L.x32);
+  }
+  hipFree(c->tab64);
+  hipFree(c->tab32);
+  hipFree(c->r);
+  hipFree(c->z);
+  hipFree(c->p);
+  hipFree(c->q);
+  hipFree(c->scal);
+  hipFree(c->partial);
+  hipFree(c->partial2);
+  hipFree(c->active);
+  if (c->hbuf) hipHostFree(c->hbuf);
+  if (c->hact) hipHostFree(c->hact);
+  delete c;
+  return DGMG_OK;
+}

@@ -1,0 +1,30 @@
+// Vector kernels of the outer Krylov iteration (dgmg_blas.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace dgmg {
+
+// Upper bound of the first-stage blocks per right-hand side of a reduction;
+// partial-sum buffers hold nrhs * kRedBlocks doubles.
+constexpr int kRedBlocks = 1024;
+
+// out[r] = a_r . b_r (and out2[r] = c_r . d_r when c != nullptr), vectors
+// [nrhs][n]; deterministic for given (n, nrhs).
+hipError_t blas_dot2(const double* a, const double* b, const double* c, const double* d,
+                     long long n, int nrhs, double* partial, double* partial2, double* out,
+                     double* out2, hipStream_t s);
+// CG update with alpha = rz / pq per active right-hand side; rr = |r|^2.
+hipError_t blas_update_xr(double* x, double* r, const double* p, const double* q, const double* rz,
+                          const double* pq, const int* active, long long n, int nrhs,
+                          double* alpha, double* partial, double* rr, hipStream_t s);
+// p = z + beta p per active right-hand side.
+hipError_t blas_update_p(double* p, const double* z, const double* rz_new, const double* rz_old,
+                         const double* zq, const double* alpha, const int* active, int flexible,
+                         long long n, int nrhs, hipStream_t s);
+hipError_t blas_f64_to_f32(const double* a, float* b, long long n, hipStream_t s);
+hipError_t blas_f32_to_f64(const float* a, double* b, long long n, hipStream_t s);
+hipError_t blas_zero_f64(double* a, long long n, hipStream_t s);
+hipError_t blas_zero_f32(float* a, long long n, hipStream_t s);
+hipError_t blas_sub(const double* a, const double* b, double* y, long long n, hipStream_t s);
+
+}  // namespace dgmg

@@ -1,0 +1,190 @@
+// Vector kernels of the outer Krylov iteration: deterministic batched dot
+// products (fixed two-stage tree), the fused CG updates with per-right-hand-
+// side masks, precision conversion and fills.  Vectors are [nrhs][n] with a
+// per-RHS stride; scalars are device arrays of nrhs doubles.
+#include <hip/hip_runtime.h>
+
+#include "dgmg_blas.h"
+
+namespace dgmg {
+namespace {
+
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// partial[r][blk] = sum over the block's grid-stride share of a_r . b_r
+// (and, if c != nullptr, partial2 = c_r . d_r)
+__global__ void __launch_bounds__(kRedThreads)
+k_dot2(const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ c,
+       const double* __restrict__ d, long long n, double* __restrict__ partial,
+       double* __restrict__ partial2) {
+  __shared__ double sh[kRedThreads];
+  const long long off = (long long)blockIdx.y * n;
+  double s1 = 0.0, s2 = 0.0;
+  const long long stride = (long long)gridDim.x * kRedThreads;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
+    s1 += a[off + i] * b[off + i];
+    if (c) s2 += c[off + i] * d[off + i];
+  }
+  const double r1 = block_sum(s1, sh);
+  if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r1;
+  if (c) {
+    __syncthreads();
+    const double r2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) partial2[blockIdx.y * gridDim.x + blockIdx.x] = r2;
+  }
+}
+
+// out[r] = sum_blk partial[r][blk] in a fixed order
+__global__ void __launch_bounds__(kRedThreads)
+k_finalize(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+  __shared__ double sh[kRedThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kRedThreads) s += partial[blockIdx.x * nblk + i];
+  const double r = block_sum(s, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = r;
+}
+
+// x += alpha p, r -= alpha q with alpha = rz/pq for active right-hand sides;
+// partial sums of |r|^2.
+__global__ void __launch_bounds__(kRedThreads)
+k_update_xr(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+            const double* __restrict__ q, const double* __restrict__ rz,
+            const double* __restrict__ pq, const int* __restrict__ active, long long n,
+            double* __restrict__ alpha_out, double* __restrict__ partial) {
+  __shared__ double sh[kRedThreads];
+  const int rhs = blockIdx.y;
+  const long long off = (long long)rhs * n;
+  const bool act = active[rhs] != 0;
+  const double alpha = act ? rz[rhs] / pq[rhs] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) alpha_out[rhs] = alpha;
+  double s = 0.0;
+  const long long stride = (long long)gridDim.x * kRedThreads;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
+    double ri = r[off + i];
+    if (act) {
+      x[off + i] += alpha * p[off + i];
+      ri -= alpha * q[off + i];
+      r[off + i] = ri;
+    }
+    s += ri * ri;
+  }
+  const double red = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[rhs * gridDim.x + blockIdx.x] = red;
+}
+
+// p = z + beta p for active right-hand sides; beta = rz_new/rz_old (standard)
+// or -alpha zq / rz_old (flexible: z^T (r_new - r_old) / rz_old).
+__global__ void __launch_bounds__(kRedThreads)
+k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ rz_new,
+           const double* __restrict__ rz_old, const double* __restrict__ zq,
+           const double* __restrict__ alpha, const int* __restrict__ active, int flexible,
+           long long n) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const long long off = (long long)rhs * n;
+  const double beta = flexible ? (-alpha[rhs] * zq[rhs] / rz_old[rhs]) : (rz_new[rhs] / rz_old[rhs]);
+  const long long stride = (long long)gridDim.x * kRedThreads;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride)
+    p[off + i] = z[off + i] + beta * p[off + i];
+}
+
+template <typename S, typename T>
+__global__ void __launch_bounds__(kRedThreads)
+k_convert(const S* __restrict__ a, T* __restrict__ b, long long n) {
+  const long long stride = (long long)gridDim.x * kRedThreads;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride)
+    b[i] = (T)a[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+k_fill(T* __restrict__ a, T v, long long n) {
+  const long long stride = (long long)gridDim.x * kRedThreads;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) a[i] = v;
+}
+
+// y = a - b  (residual r = b - A x)
+__global__ void __launch_bounds__(kRedThreads)
+k_sub(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y,
+      long long n) {
+  const long long stride = (long long)gridDim.x * kRedThreads;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride)
+    y[i] = a[i] - b[i];
+}
+
+int grid_for(long long n) {
+  long long g = (n + kRedThreads * 4 - 1) / (kRedThreads * 4);
+  if (g < 1) g = 1;
+  if (g > kRedBlocks) g = kRedBlocks;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t blas_dot2(const double* a, const double* b, const double* c, const double* d,
+                     long long n, int nrhs, double* partial, double* partial2, double* out,
+                     double* out2, hipStream_t s) {
+  const int g = grid_for(n);
+  hipLaunchKernelGGL(k_dot2, dim3(g, nrhs), dim3(kRedThreads), 0, s, a, b, c, d, n, partial,
+                     partial2);
+  hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial, g, out);
+  if (c) hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial2, g, out2);
+  return hipGetLastError();
+}
+
+hipError_t blas_update_xr(double* x, double* r, const double* p, const double* q, const double* rz,
+                          const double* pq, const int* active, long long n, int nrhs,
+                          double* alpha, double* partial, double* rr, hipStream_t s) {
+  const int g = grid_for(n);
+  hipLaunchKernelGGL(k_update_xr, dim3(g, nrhs), dim3(kRedThreads), 0, s, x, r, p, q, rz, pq,
+                     active, n, alpha, partial);
+  hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial, g, rr);
+  return hipGetLastError();
+}
+
+hipError_t blas_update_p(double* p, const double* z, const double* rz_new, const double* rz_old,
+                         const double* zq, const double* alpha, const int* active, int flexible,
+                         long long n, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p, dim3(grid_for(n), nrhs), dim3(kRedThreads), 0, s, p, z, rz_new,
+                     rz_old, zq, alpha, active, flexible, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_f64_to_f32(const double* a, float* b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n)), dim3(kRedThreads), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_f32_to_f64(const float* a, double* b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(n)), dim3(kRedThreads), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_zero_f64(double* a, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(n)), dim3(kRedThreads), 0, s, a, 0.0, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_zero_f32(float* a, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(n)), dim3(kRedThreads), 0, s, a, 0.0f, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_sub(const double* a, const double* b, double* y, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(kRedThreads), 0, s, a, b, y, n);
+  return hipGetLastError();
+}
+
+}  // namespace dgmg

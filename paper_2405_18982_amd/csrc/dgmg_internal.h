@@ -1,0 +1,76 @@
+// Internal declarations shared by the host orchestration (dgmg_api.cpp) and
+// the per-(dimension, degree) kernel translation units (dgmg_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dgmg {
+
+constexpr int kMaxDegree = 7;
+
+// Reference (h = 1, kappa = 1) 1-D tables of Q_K on a two-cell patch, in the
+// arithmetic type T of the kernels that read them.  Built on the host in FP64
+// (setup.cpp) and uploaded once per context.
+//   M   : cell mass  int phi_mu phi_nu
+//   Lc  : 1-D SIPG cell block with interior faces on both sides
+//         K + sigma (e0 e0^T + e1 e1^T) + (e0 d0^T + d0 e0^T)/2 - (e1 d1^T + d1 e1^T)/2
+//   d0, d1 : phi'(0), phi'(1)
+//   S[t], lam[t] : fast-diagonalisation eigenpairs of patch type t, padded to E
+//   P   : stacked prolongation, P[(o n + mu) n + nu] = phi_nu((xi_mu + o)/2)
+template <int K, typename T>
+struct Tab {
+  static constexpr int n = K + 1;
+  static constexpr int E = 2 * n;
+  T M[n * n];
+  T Lc[n * n];
+  T d0[n];
+  T d1[n];
+  T sigma;
+  T S[4][E * E];
+  T lam[4][E];
+  T P[E * n];
+};
+
+// The patches of one launch: patch m = (m_0, .., m_{D-1}), m_i < cnt[i], has
+// its lower-left cell at lo_i = off[i] + 2 m_i and covers cells lo_i, lo_i + 1.
+struct PatchGrid {
+  int N;       // cells per direction on the level
+  int cnt[3];  // patches per direction
+  int off[3];  // 0 or 1: colour bit per direction
+  int npatch;  // product of cnt
+};
+
+// Host-visible launchers of one (D, K) instantiation.  All vectors are
+// [nrhs][ndof] device arrays; `tab` points to a device Tab<K, T>.
+template <typename T>
+struct KernelSet {
+  hipError_t (*apply)(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
+                      long long ndof, hipStream_t s);
+  hipError_t (*mass)(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
+                     long long ndof, hipStream_t s);
+  hipError_t (*smooth)(const void* tab, PatchGrid g, T scale, T inv_scale, int local_variant,
+                       T* x, const T* b, int nrhs, long long ndof, hipStream_t s);
+  hipError_t (*restrict_residual)(const void* tab, PatchGrid g, T scale, const T* x, const T* b,
+                                  T* bc, int nrhs, long long ndof, long long ndof_c,
+                                  hipStream_t s);
+  hipError_t (*prolongate_add)(const void* tab, PatchGrid g, const T* xc, T* x, int nrhs,
+                               long long ndof, long long ndof_c, hipStream_t s);
+  hipError_t (*coarse)(const void* tab, T inv_scale, const T* b, T* x, int nrhs,
+                       long long ndof, hipStream_t s);
+};
+
+// Registration entry of one kernel translation unit.
+struct KernelEntry {
+  int dim;
+  int degree;
+  KernelSet<double> f64;
+  KernelSet<float> f32;
+};
+
+}  // namespace dgmg
+
+// Each kernel TU defines dgmg_kernels_d<D>_k<K>(KernelEntry*).
+#define DGMG_KERNEL_ENTRY_NAME(D, K) dgmg_kernels_d##D##_k##K
+#define DGMG_DECLARE_ENTRY(D, K) \
+  extern "C" void DGMG_KERNEL_ENTRY_NAME(D, K)(dgmg::KernelEntry * e);

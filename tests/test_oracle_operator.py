@@ -140,3 +140,13 @@ def test_planted_sign_error_is_caught(monkeypatch):
     assert np.abs(A @ u - b).max() > 1e-3 * np.abs(b).max()
     A2 = assemble_quadrature(d, k, N, sig(k))
     assert abs(A - A2).max() > 1e-3 * abs(A2).max()
+
+
+@pytest.mark.parametrize("d,k,N", [(2, 2, 4), (3, 1, 4), (3, 2, 3)])
+def test_vectorised_patch_indices_equal_loop_definition(d, k, N):
+    from oracle.patches import colour, kept_mask, patch_dofs
+    ps = PatchSet(d, k, N)
+    for j, v in enumerate(ps.verts):
+        assert np.array_equal(ps.tiles[j], patch_dofs(d, k, N, v))
+        assert np.array_equal(ps.masks[j], kept_mask(d, k, N, v))
+        assert ps.colours[j] == colour(v)
