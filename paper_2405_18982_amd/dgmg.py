@@ -62,6 +62,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2405_18982_amd.build`")
+        # torch bundles its own HIP runtime (same soname as ROCm's).  Loading
+        # torch first makes libdgmg bind to that copy, so the process holds a
+        # single runtime that both torch tensors and libdgmg kernels use.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
@@ -102,6 +106,11 @@ class Problem:
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("libdgmg needs a GPU: torch.cuda.is_available() is False")
+        # libdgmg runs on the HIP runtime torch has loaded: let torch create the
+        # device context first so both share one initialised runtime.
+        torch.cuda.init()
+        torch.empty(1, device="cuda")
+        torch.cuda.synchronize()
         self.dim, self.k, self.L = dim, k, L
         self.sigma = 2.0 * (k + 1) ** 2 if sigma is None else float(sigma)
         self.kappa = float(kappa)
