@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -89,7 +90,10 @@ void fill_tab(const dgmg::HostTables& H, std::vector<unsigned char>& out) {
   t->sigma = (T)H.sigma;
   for (int ty = 0; ty < 4; ++ty) {
     for (int i = 0; i < E * E; ++i) t->S[ty][i] = (T)H.S[ty][i];
-    for (int i = 0; i < E; ++i) t->lam[ty][i] = (T)H.lam[ty][i];
+    // unused eigenvalue slots: a huge finite value instead of +inf, so that the
+    // kernels' reciprocal (estimate + Newton steps) returns ~0 without NaNs
+    for (int i = 0; i < E; ++i)
+      t->lam[ty][i] = std::isinf(H.lam[ty][i]) ? (T)(sizeof(T) == 8 ? 1e300 : 1e30) : (T)H.lam[ty][i];
   }
   for (int i = 0; i < E * n; ++i) t->P[i] = (T)H.P[i];
 }
@@ -120,6 +124,7 @@ struct dgmg_ctx {
   hipStream_t stream = nullptr;
   void* tab64 = nullptr;
   void* tab32 = nullptr;
+
   // Krylov workspace (finest level, FP64) and scalars
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double* scal = nullptr;  // kNumScal arrays of nrhs_max
@@ -153,9 +158,21 @@ T* dalloc(long long count, hipError_t& e) {
   return e == hipSuccess ? (T*)p : nullptr;
 }
 
+// XCD-aware patch numbering (on unless DGMG_XCD_REMAP=0; the switch exists
+// to measure its effect).
+int xcd_remap_flag() {
+  static int flag = -1;
+  if (flag < 0) {
+    const char* e = std::getenv("DGMG_XCD_REMAP");
+    flag = (e && e[0] == '0') ? 0 : 1;
+  }
+  return flag;
+}
+
 PatchGrid grid_colour0(const dgmg_ctx* c, int N) {
   PatchGrid g{};
   g.N = N;
+  g.xcd_remap = xcd_remap_flag();
   g.npatch = 1;
   for (int i = 0; i < 3; ++i) {
     g.cnt[i] = (i < c->dim) ? N / 2 : 1;
@@ -168,6 +185,7 @@ PatchGrid grid_colour0(const dgmg_ctx* c, int N) {
 PatchGrid grid_colour(const dgmg_ctx* c, int N, int colour) {
   PatchGrid g{};
   g.N = N;
+  g.xcd_remap = xcd_remap_flag();
   g.npatch = 1;
   for (int i = 0; i < 3; ++i) {
     if (i < c->dim) {
@@ -194,7 +212,6 @@ template <>
 const KernelSet<float>& kset<float>(const dgmg_ctx* c) { return c->ks->f32; }
 template <typename T>
 void* tab_of(const dgmg_ctx* c) { return sizeof(T) == 8 ? c->tab64 : c->tab32; }
-
 dgmg_status check_ready(dgmg_ctx* c) {
   if (!c) return DGMG_ERR_ARG;
   if (!c->ready) return fail(c, DGMG_ERR_STATE, "dgmg_setup_levels has not been called");

@@ -17,6 +17,7 @@ constexpr int kMaxDegree = 7;
 //         K + sigma (e0 e0^T + e1 e1^T) + (e0 d0^T + d0 e0^T)/2 - (e1 d1^T + d1 e1^T)/2
 //   d0, d1 : phi'(0), phi'(1)
 //   S[t], lam[t] : fast-diagonalisation eigenpairs of patch type t, padded to E
+//         (unused eigenvalue slots hold a huge finite value)
 //   P   : stacked prolongation, P[(o n + mu) n + nu] = phi_nu((xi_mu + o)/2)
 template <int K, typename T>
 struct Tab {
@@ -39,6 +40,7 @@ struct PatchGrid {
   int cnt[3];  // patches per direction
   int off[3];  // 0 or 1: colour bit per direction
   int npatch;  // product of cnt
+  int xcd_remap;  // 1: give each XCD a contiguous range of patches
 };
 
 // Host-visible launchers of one (D, K) instantiation.  All vectors are

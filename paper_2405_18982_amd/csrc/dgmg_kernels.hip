@@ -4,28 +4,33 @@
 //
 // Every kernel works on "patches": the 2^D cells with coordinates lo_i and
 // lo_i + 1 in each direction i.  A patch carries E = 2(K+1) nodes per
-// direction (patch-local index p = n c + a for cell c in {0,1}, node a).  One
-// workgroup owns PPB patches; each patch's node tile sits in LDS with padded
-// strides (SY, SZ).  Work inside a patch proceeds in phases separated by
-// barriers; in a phase along direction `dir` each thread owns one 1-D line of
-// the tile (all other coordinates fixed), pulls it into registers, contracts
-// it with the 1-D matrices (wave-uniform, read through scalar loads from the
-// Tab struct) and writes the result back to its own line.
+// direction (patch-local index p = n c + a for cell c in {0,1}, node a).  A
+// workgroup owns PPB patches, TPP = E^(D-1) threads each (one wave per patch
+// for 3-D K <= 3, several 2-D patches per wave).  Work proceeds in phases
+// separated by barriers; in a phase along direction `dir` each thread owns one
+// 1-D line of the patch (all other coordinates fixed), contracts it in
+// registers with the 1-D matrices (wave-uniform operands read through scalar
+// loads from the Tab struct) and hands the result to the next phase through
+// LDS.  The first phase (along x) reads its lines straight from global memory:
+// an x-line of a patch is two contiguous cell rows, and its outside neighbours
+// across the x-faces are the adjacent rows, so x itself never passes through
+// LDS.  Smoothers keep that x-line in registers and finish with another
+// x-phase that writes x + delta back as contiguous rows.
 //
 // Operator (Sec. 2.2): on a Cartesian mesh A = sum_i (x)(M .. L_i .. M), with
 // reference matrices (h = 1) and A_h = kappa h^(D-2) A_ref.  The 1-D SIPG
-// operator restricted to the patch is applied per cell block (Lc) plus rank-2
-// face couplings: for a cell with trace t and derivative g of its neighbour
-// across a face, the rows pick up e (alpha) + d (beta) with
-//   left neighbour  (its x=1 side):  alpha = g/2 - sigma t, beta = -t/2 (e0, d0)
-//   right neighbour (its x=0 side):  alpha = -sigma t - g/2, beta =  t/2 (e1, d1)
-// and on a domain-boundary face the Nitsche correction of the cell block,
-//   x=0: alpha = (d0.v)/2, beta = v_0/2;   x=1: alpha = -(d1.v)/2, beta = -v_k/2.
-// Face data of the outside neighbours ("ext") is gathered per face node in
-// the load phase; faces normal to y and z are pre-contracted with the
-// tangential masses so that the sum-factorised order
-//   a = M_x x, b = L_x x;  c = M_y b + L_y a, d = M_y a;  y = M_z c + L_z d
-// needs only one pass per direction.
+// operator restricted to the patch is applied per cell block (Lc: both faces
+// interior) plus rank-2 face terms e alpha + d beta:
+//   interior face, neighbour on the left  (its x=1 side, trace t, derivative g):
+//       alpha = g/2 - sigma t, beta = -t/2   on the rows e0, d0
+//   interior face, neighbour on the right (its x=0 side):
+//       alpha = -sigma t - g/2, beta = t/2   on the rows e1, d1
+//   domain-boundary face (Nitsche), from the cell's own line v:
+//       x=0: alpha = (d0.v)/2, beta = v_0/2;  x=1: alpha = -(d1.v)/2, beta = -v_k/2
+// Face data of interior neighbours across y- and z-faces ("ext") is gathered
+// per face node into LDS and contracted with the tangential masses on the fly,
+// giving the sum-factorised order
+//   a = M_x x, b = L_x x;  c = M_y b + L_y a, d = M_y a;  y = M_z c + L_z d.
 #include "dgmg_internal.h"
 
 #ifndef DGMG_D
@@ -46,30 +51,23 @@ constexpr int NL = (D == 2) ? E : E * E;            // lines per direction
 constexpr int NC = (D == 2) ? n * n : n * n * n;    // nodes per cell
 constexpr int NCP = (D == 2) ? 4 : 8;               // cells per patch
 constexpr int SY = E + 1;                           // padded LDS strides
-constexpr int SZ = (D == 3) ? E * SY + 1 : 0;
+constexpr int SZ = (D == 3) ? E * SY : 0;
 constexpr int TS = (D == 2) ? E * SY : E * SZ;      // padded tile size
-constexpr int NEXT = D * 2 * 2 * NL;                // ext face data per patch
+constexpr int NF = (D == 2) ? E : E * E;            // nodes of one patch face
 
 // threads per patch (one per line) and patches per workgroup
 constexpr int TPP = NL;
+static_assert(TPP == NL, "each thread owns exactly one line per phase");
 constexpr int PPB_DEFAULT = (D == 3)
-    ? (K == 1 ? 4 : K == 2 ? 7 : K == 3 ? 2 : K == 4 ? 2 : 1)
+    ? (K == 1 ? 4 : 1)
     : (K == 1 ? 16 : K == 2 ? 10 : K == 3 ? 8 : K == 4 ? 6 : K == 5 ? 5 : 4);
 
-__host__ __device__ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
-
-__device__ __forceinline__ int toff(int px, int py, int pz) { return px + py * SY + pz * SZ; }
-
-// base offset and stride of line l along direction dir
+// base offset and stride of LDS line l along direction dir
 __device__ __forceinline__ void line_geom(int dir, int l, int& base, int& stride) {
   const int a = l % E, b = l / E;
   if (dir == 0) { base = a * SY + b * SZ; stride = 1; }
   else if (dir == 1) { base = a + b * SZ; stride = SY; }
   else { base = a + b * SY; stride = SZ; }
-}
-
-__device__ __forceinline__ int ext_idx(int dir, int side, int comp, int l) {
-  return ((dir * 2 + side) * 2 + comp) * NL + l;
 }
 
 template <typename T>
@@ -100,10 +98,30 @@ __device__ __forceinline__ void line_mass(const Tab<K, T>* __restrict__ t, const
     }
 }
 
-// o (+)= 1-D SIPG on the patch line v with outside couplings (aL, bL, aR, bR)
+// 1/x from the hardware reciprocal estimate refined by one Newton step
+// r <- r (2 - x r); the squared relative error of the estimate is far below
+// the FP64 tolerance of the smoother.  x is a positive finite sum of patch
+// eigenvalues (unused slots carry a huge finite value, giving ~0).
+__device__ __forceinline__ double recip(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+
+// Couplings of a patch line to what lies beyond its two outer faces.
+template <typename T>
+struct Sides {
+  bool bl, br;   // left / right outer face on the domain boundary (Nitsche)
+  T aL, bL, aR, bR;  // interior-neighbour couplings (ignored on boundary sides)
+};
+
+// o (+)= 1-D SIPG of the patch line v
 template <typename T, bool ACC>
 __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const Line<T>& v,
-                                          T aL, T bL, T aR, T bR, Line<T>& o) {
+                                          const Sides<T>& sd, Line<T>& o) {
   const T sg = t->sigma;
   const T half = T(0.5);
 #pragma unroll
@@ -115,7 +133,7 @@ __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const
       for (int nu = 0; nu < n; ++nu) s += t->Lc[mu * n + nu] * v.v[c * n + nu];
       o.v[c * n + mu] = s;
     }
-  // coupling across the face between the two patch cells
+  // face between the two patch cells
   const T tR = v.v[n];      // trace of the right cell at its x=0 side
   const T tL = v.v[n - 1];  // trace of the left cell at its x=1 side
   T gR = T(0), gL = T(0);
@@ -123,6 +141,21 @@ __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const
   for (int j = 0; j < n; ++j) {
     gR += t->d0[j] * v.v[n + j];
     gL += t->d1[j] * v.v[j];
+  }
+  T aL = sd.aL, bL = sd.bL, aR = sd.aR, bR = sd.bR;
+  if (sd.bl) {  // Nitsche correction of the left cell (uniform per patch)
+    T g0 = T(0);
+#pragma unroll
+    for (int j = 0; j < n; ++j) g0 += t->d0[j] * v.v[j];
+    aL = half * g0;
+    bL = half * v.v[0];
+  }
+  if (sd.br) {
+    T g1 = T(0);
+#pragma unroll
+    for (int j = 0; j < n; ++j) g1 += t->d1[j] * v.v[n + j];
+    aR = -half * g1;
+    bR = -half * v.v[E - 1];
   }
   const T bLc = half * tR;   // beta seen by the left cell from its right neighbour
   const T bRc = -half * tL;  // beta seen by the right cell from its left neighbour
@@ -192,6 +225,17 @@ __device__ __forceinline__ void line_S(const Tab<K, T>* __restrict__ t, int ty, 
   }
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Renumber them so that XCD j works on the j-th contiguous range of patches:
+// neighbouring patches, whose face traces a patch reads, then sit in the
+// same L2.  Bijective on [0, nblocks).
+__device__ __forceinline__ int xcd_block(int b, int nblocks, int remap) {
+  if (!remap || nblocks < 8) return b;
+  const int q = nblocks / 8, r = nblocks % 8;
+  const int xcd = b % 8, idx = b / 8;
+  return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
 // Patch coordinates of patch index pid of a launch.
 struct PatchPos {
   int lo[3];
@@ -229,206 +273,324 @@ __device__ __forceinline__ long long node_offset(int N, const PatchPos& P, int p
   return cell * NC + ax + n * (ay + n * az);
 }
 
-// Copy the patch's 2^D cells from global to the LDS tile (coalesced per cell).
-template <typename T>
-__device__ __forceinline__ void load_tile(const T* __restrict__ x, int N, const PatchPos& P,
-                                          int lane, T* tile) {
-  for (int i = lane; i < NCP * NC; i += TPP) {
-    const int c = i / NC, loc = i % NC;
-    const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
-    const int ax = loc % n, ay = (loc / n) % n, az = loc / (n * n);
-    const long long cell = cell_index(N, P.lo[0] + cx, P.lo[1] + cy, (D == 3) ? P.lo[2] + cz : 0);
-    tile[toff(cx * n + ax, cy * n + ay, cz * n + az)] = x[cell * NC + loc];
-  }
+// Global offset of the first node of the patch's x-line (py, pz) (cell lo_x).
+__device__ __forceinline__ long long xrow_offset(int N, const PatchPos& P, int py, int pz) {
+  return node_offset(N, P, 0, py, (D == 3) ? pz : 0);
 }
 
-// Face data of the 2D sides of the patch.  For face node l of direction dir,
-// side s: the neighbour cell across the patch boundary (or, on the domain
-// boundary, the patch's own cell for the Nitsche correction) is read along
-// dir.  MODE 0: alpha and beta (operator rows on all patch nodes);
-// MODE 1: smoother, beta only for interior faces (alpha acts on dropped rows);
-// MODE 2: paper-literal smoother, interior faces ignored.
+// Side flags and x-face couplings of x-line (py, pz), read from the rows of
+// the outside neighbours.  MODE 0: full operator rows; 1: smoother (only the
+// traces matter, alpha acts on dropped rows); 2: paper-literal smoother
+// (interior neighbours ignored).
 template <typename T, int MODE>
-__device__ __forceinline__ void load_ext(const Tab<K, T>* __restrict__ t, const T* __restrict__ x,
-                                         int N, const PatchPos& P, int lane, T* ext) {
+__device__ __forceinline__ Sides<T> xline_sides(const Tab<K, T>* __restrict__ t, const T* __restrict__ x,
+                                                int N, const PatchPos& P, long long row0) {
   const T half = T(0.5);
   const T sg = t->sigma;
-  for (int i = lane; i < D * 2 * NL; i += TPP) {
-    const int l = i % NL;
-    const int side = (i / NL) & 1;
-    const int dir = i / (2 * NL);
-    // tangential tile coordinates of face node l
-    int pc[3] = {0, 0, 0};
-    {
-      const int a = l % E, b = l / E;
-      if (dir == 0) { pc[1] = a; pc[2] = b; }
-      else if (dir == 1) { pc[0] = a; pc[2] = b; }
-      else { pc[0] = a; pc[1] = b; }
-    }
-    int cc[3], ac[3];
+  Sides<T> sd;
+  sd.bl = (P.lo[0] == 0);
+  sd.br = (P.lo[0] + 1 == N - 1);
+  sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  if (MODE != 2) {
+    if (!sd.bl) {
+      const T* r = x + row0 - NC;
+      const T tr = r[K];
+      sd.bL = -half * tr;
+      if (MODE == 0) {
+        T g = T(0);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) { cc[j] = P.lo[j] + pc[j] / n; ac[j] = pc[j] % n; }
-    const int nb = (side == 0) ? P.lo[dir] - 1 : P.lo[dir] + 2;
-    const bool interior = (nb >= 0 && nb < N);
-    const int strideN = (dir == 0) ? 1 : (dir == 1) ? n : n * n;
-    T alpha = T(0), beta = T(0);
-    if (interior) {
-      if (MODE != 2) {
-        cc[dir] = nb;
-        ac[dir] = 0;
-        const long long base = cell_index(N, cc[0], cc[1], cc[2]) * NC + ac[0] + n * (ac[1] + n * ac[2]);
-        const T tr = x[base + (long long)((side == 0) ? K : 0) * strideN];
-        if (MODE == 0) {
-          T g = T(0);
-#pragma unroll
-          for (int j = 0; j < n; ++j) g += ((side == 0) ? t->d1[j] : t->d0[j]) * x[base + (long long)j * strideN];
-          alpha = (side == 0) ? (half * g - sg * tr) : (-sg * tr - half * g);
-        }
-        beta = (side == 0) ? -half * tr : half * tr;
+        for (int j = 0; j < n; ++j) g += t->d1[j] * r[j];
+        sd.aL = half * g - sg * tr;
       }
-    } else {
-      cc[dir] = (side == 0) ? P.lo[dir] : P.lo[dir] + 1;
-      ac[dir] = 0;
-      const long long base = cell_index(N, cc[0], cc[1], cc[2]) * NC + ac[0] + n * (ac[1] + n * ac[2]);
-      T g = T(0);
-#pragma unroll
-      for (int j = 0; j < n; ++j) g += ((side == 0) ? t->d0[j] : t->d1[j]) * x[base + (long long)j * strideN];
-      const T tr = x[base + (long long)((side == 0) ? 0 : K) * strideN];
-      alpha = (side == 0) ? half * g : -half * g;
-      beta = (side == 0) ? half * tr : -half * tr;
     }
-    ext[ext_idx(dir, side, 0, l)] = alpha;
-    ext[ext_idx(dir, side, 1, l)] = beta;
+    if (!sd.br) {
+      const T* r = x + row0 + 2 * NC;
+      const T tr = r[0];
+      sd.bR = half * tr;
+      if (MODE == 0) {
+        T g = T(0);
+#pragma unroll
+        for (int j = 0; j < n; ++j) g += t->d0[j] * r[j];
+        sd.aR = -sg * tr - half * g;
+      }
+    }
+  }
+  return sd;
+}
+
+// Raw face data of interior neighbours across y- (and z-) faces.  Entry i
+// enumerates (dir, side, face node f); f = a + E b with (a, b) the tangential
+// patch coordinates in increasing direction order.  NCOMP = 2 stores
+// (alpha, beta), NCOMP = 1 stores beta only.  Layout: ext[(fd * 2 + side) *
+// NCOMP + comp][f] with fd = dir - 1.
+template <typename T, int MODE>
+__device__ __forceinline__ void gather_ext(const Tab<K, T>* __restrict__ t, const T* __restrict__ x,
+                                           int N, const PatchPos& P, int lane, T* ext) {
+  constexpr int NCOMP = (MODE == 0) ? 2 : 1;
+  constexpr int FD0 = (MODE == 0) ? 0 : 1;  // smoothers read y-face traces from global
+  const T half = T(0.5);
+  const T sg = t->sigma;
+  for (int i = lane; i < (D - 1 - FD0) * 2 * NF; i += TPP) {
+    const int f = i % NF;
+    const int side = (i / NF) & 1;
+    const int fd = i / (2 * NF) + FD0;
+    const int dir = fd + 1;
+    const int nb = (side == 0) ? P.lo[dir] - 1 : P.lo[dir] + 2;
+    T alpha = T(0), beta = T(0);
+    if (MODE != 2 && nb >= 0 && nb < N) {
+      const int a = f % E, b = f / E;
+      int cc[3], ac[3];
+      cc[0] = P.lo[0] + a / n;
+      ac[0] = a % n;
+      if (dir == 1) { cc[2] = P.lo[2] + b / n; ac[2] = b % n; }
+      else { cc[1] = P.lo[1] + b / n; ac[1] = b % n; }
+      if (D == 2) { cc[2] = 0; ac[2] = 0; }
+      cc[dir] = nb;
+      ac[dir] = 0;
+      const int strideN = (dir == 1) ? n : n * n;
+      const long long base = cell_index(N, cc[0], cc[1], cc[2]) * NC + ac[0] + n * (ac[1] + n * ac[2]);
+      const T tr = x[base + (long long)((side == 0) ? K : 0) * strideN];
+      beta = (side == 0) ? -half * tr : half * tr;
+      if (MODE == 0) {
+        T g = T(0);
+#pragma unroll
+        for (int j = 0; j < n; ++j) g += ((side == 0) ? t->d1[j] : t->d0[j]) * x[base + (long long)j * strideN];
+        alpha = (side == 0) ? (half * g - sg * tr) : (-sg * tr - half * g);
+      }
+    }
+    if (NCOMP == 2) {
+      ext[((fd * 2 + side) * 2 + 0) * NF + f] = alpha;
+      ext[((fd * 2 + side) * 2 + 1) * NF + f] = beta;
+    } else {
+      ext[((fd - FD0) * 2 + side) * NF + f] = beta;
+    }
   }
 }
 
-// Tangential mass contraction of the ext arrays, lines along direction
-// `along` of faces normal to `dir` (face index l = a + E b).
+// mass-contract ext entries along the first tangential coordinate for the
+// value at (a, b): sum over the cell block of a
 template <typename T>
-__device__ __forceinline__ void ext_mass_line(const Tab<K, T>* __restrict__ t, T* ext, int dir,
-                                              int along_first, int j) {
-  // j enumerates (side, comp, fixed coordinate): 4 * E lines
-  const int fixed = j % E;
-  const int sc = j / E;  // side*2 + comp
-  T* a = ext + (dir * 4 + sc) * NL;
-  const int base = along_first ? fixed * E : fixed;
-  const int stride = along_first ? 1 : E;
-  Line<T> v, o;
+__device__ __forceinline__ T ext_mx(const Tab<K, T>* __restrict__ t, const T* arr, int a, int b) {
+  const int c0 = (a / n) * n, mu = a % n;
+  T s = T(0);
 #pragma unroll
-  for (int p = 0; p < E; ++p) v.v[p] = a[base + p * stride];
-  line_mass<T>(t, v, o);
+  for (int nu = 0; nu < n; ++nu) s += t->M[mu * n + nu] * arr[c0 + nu + E * b];
+  return s;
+}
+template <typename T>
+__device__ __forceinline__ T ext_my(const Tab<K, T>* __restrict__ t, const T* arr, int a, int b) {
+  const int c0 = (b / n) * n, mu = b % n;
+  T s = T(0);
 #pragma unroll
-  for (int p = 0; p < E; ++p) a[base + p * stride] = o.v[p];
+  for (int nu = 0; nu < n; ++nu) s += t->M[mu * n + nu] * arr[a + E * (c0 + nu)];
+  return s;
 }
 
-// The three (two) sum-factorisation passes of y = A_ref x on the patch tile.
-// After the call the tile A holds, for D = 3, nothing useful, and the output
-// lines are handed to `emit(line index, Line)` in the last (z / y) phase.
-// bufA holds x on entry; bufB is scratch.
-template <typename T, typename Emit>
-__device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t, T* bufA, T* bufB,
-                                                T* ext, int lane, bool active, Emit emit) {
-  // `active` gates the work only: every thread of the block meets every barrier.
-  // X phase: a = M_x x -> A, b = L_x x -> B; ext of y/z faces: M_x
-  {
-    const int nextl = (D == 3) ? 8 * E : 4;
-    for (int i = lane; active && i < NL + nextl; i += TPP) {
-      if (i < NL) {
-        int base, stride;
-        line_geom(0, i, base, stride);
-        Line<T> v, a, b;
-        load_line(bufA, base, stride, v);
-        line_mass<T>(t, v, a);
-        line_sipg<T, false>(t, v, ext[ext_idx(0, 0, 0, i)], ext[ext_idx(0, 0, 1, i)],
-                            ext[ext_idx(0, 1, 0, i)], ext[ext_idx(0, 1, 1, i)], b);
-        store_line(bufA, base, stride, a);
-        store_line(bufB, base, stride, b);
-      } else {
-        const int j = i - NL;
-        if (D == 3) {
-          if (j < 4 * E) ext_mass_line<T>(t, ext, 1, 1, j);
-          else ext_mass_line<T>(t, ext, 2, 1, j - 4 * E);
-        } else {
-          // 2-D: faces normal to y are indexed by px only; 4 lines of length E
-          T* a = ext + (1 * 4 + j) * NL;
-          Line<T> v, o;
+// Sides of a y-line (px, pz) (D = 3) or (px) (D = 2): ext_y contracted with M_x.
+template <typename T, int NCOMP>
+__device__ __forceinline__ Sides<T> yline_sides(const Tab<K, T>* __restrict__ t, const T* ext,
+                                                int N, const PatchPos& P, int px, int pz) {
+  Sides<T> sd;
+  sd.bl = (P.lo[1] == 0);
+  sd.br = (P.lo[1] + 1 == N - 1);
+  sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  if (NCOMP == 2) {
+    if (!sd.bl) { sd.aL = ext_mx<T>(t, ext + 0 * NF, px, pz); sd.bL = ext_mx<T>(t, ext + 1 * NF, px, pz); }
+    if (!sd.br) { sd.aR = ext_mx<T>(t, ext + 2 * NF, px, pz); sd.bR = ext_mx<T>(t, ext + 3 * NF, px, pz); }
+  } else {
+    if (!sd.bl) sd.bL = ext_mx<T>(t, ext + 0 * NF, px, pz);
+    if (!sd.br) sd.bR = ext_mx<T>(t, ext + 1 * NF, px, pz);
+  }
+  return sd;
+}
+
+// Sides of the smoother's y-line (px, pz): the traces of the y-neighbours at
+// nodes (a, k or 0, pz), a in the cell block of px, contracted with M_x
+// straight from global memory (n contiguous values per side).  MODE 2 (the
+// paper-literal kernel) ignores interior neighbours.
+template <typename T, int MODE>
+__device__ __forceinline__ Sides<T> yline_sides_global(const Tab<K, T>* __restrict__ t,
+                                                       const T* __restrict__ x, int N,
+                                                       const PatchPos& P, int px, int pz) {
+  Sides<T> sd;
+  sd.bl = (P.lo[1] == 0);
+  sd.br = (P.lo[1] + 1 == N - 1);
+  sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  if (MODE == 2) return sd;
+  const int mu = px % n;
+  const int cx = P.lo[0] + px / n;
+  const int cz = (D == 3) ? P.lo[2] + pz / n : 0;
+  const int az = (D == 3) ? pz % n : 0;
+  const T half = T(0.5);
+  if (!sd.bl) {
+    const T* r = x + cell_index(N, cx, P.lo[1] - 1, cz) * NC + K * n + az * n * n;
+    T s = T(0);
 #pragma unroll
-          for (int p = 0; p < E; ++p) v.v[p] = a[p];
-          line_mass<T>(t, v, o);
+    for (int nu = 0; nu < n; ++nu) s += t->M[mu * n + nu] * r[nu];
+    sd.bL = -half * s;
+  }
+  if (!sd.br) {
+    const T* r = x + cell_index(N, cx, P.lo[1] + 2, cz) * NC + az * n * n;
+    T s = T(0);
 #pragma unroll
-          for (int p = 0; p < E; ++p) a[p] = o.v[p];
-        }
-      }
+    for (int nu = 0; nu < n; ++nu) s += t->M[mu * n + nu] * r[nu];
+    sd.bR = half * s;
+  }
+  return sd;
+}
+
+// In the y-phase the z-face arrays are contracted along x in place (lines at
+// fixed py); in the z-phase the value at (px, py) is contracted along y.
+// z-face arrays follow the y-face arrays in the operator layout; smoothers
+// keep only the z-face traces in LDS.
+template <int NCOMP>
+__device__ __forceinline__ constexpr int extz_base() { return NCOMP == 2 ? 4 * NF : 0; }
+
+template <typename T, int NCOMP>
+__device__ __forceinline__ void extz_mass_x_line(const Tab<K, T>* __restrict__ t, T* ext, int j) {
+  const int py = j % E;
+  const int arr = j / E;  // (side * NCOMP + comp)
+  T* a = ext + extz_base<NCOMP>() + arr * NF + py * E;
+  Line<T> v, o;
+#pragma unroll
+  for (int p = 0; p < E; ++p) v.v[p] = a[p];
+  line_mass<T>(t, v, o);
+#pragma unroll
+  for (int p = 0; p < E; ++p) a[p] = o.v[p];
+}
+template <typename T, int NCOMP>
+__device__ __forceinline__ Sides<T> zline_sides(const Tab<K, T>* __restrict__ t, const T* ext,
+                                                int N, const PatchPos& P, int px, int py) {
+  Sides<T> sd;
+  sd.bl = (P.lo[2] == 0);
+  sd.br = (P.lo[2] + 1 == N - 1);
+  sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  const T* z = ext + extz_base<NCOMP>();
+  if (NCOMP == 2) {
+    if (!sd.bl) { sd.aL = ext_my<T>(t, z + 0 * NF, px, py); sd.bL = ext_my<T>(t, z + 1 * NF, px, py); }
+    if (!sd.br) { sd.aR = ext_my<T>(t, z + 2 * NF, px, py); sd.bR = ext_my<T>(t, z + 3 * NF, px, py); }
+  } else {
+    if (!sd.bl) sd.bL = ext_my<T>(t, z + 0 * NF, px, py);
+    if (!sd.br) sd.bR = ext_my<T>(t, z + 1 * NF, px, py);
+  }
+  return sd;
+}
+
+// Read x-line (py, pz) from global.
+template <typename T>
+__device__ __forceinline__ void read_xline(const T* __restrict__ x, long long row0, Line<T>& v) {
+#pragma unroll
+  for (int a = 0; a < n; ++a) {
+    v.v[a] = x[row0 + a];
+    v.v[n + a] = x[row0 + NC + a];
+  }
+}
+
+// Operator passes of y = A_ref x on the patch.  Phase X0 reads the x-lines
+// from global (and keeps them in xl for the caller), gathers the y/z face
+// data; the last pass (z in 3-D, y in 2-D) hands each output line to
+// emit(line, base, stride, y).  A, B: LDS tiles; ext: LDS face data.
+template <typename T, int MODE, typename Emit>
+__device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t, const T* __restrict__ x,
+                                                int N, const PatchPos& P, T* A, T* B, T* ext,
+                                                int lane, bool active, Line<T>& xl,
+                                                const Sides<T>& ysd_global, Emit emit) {
+  constexpr int NCOMP = (MODE == 0) ? 2 : 1;
+  // X0: a = M_x x -> A, b = L_x x -> B
+  if (active) {
+    gather_ext<T, MODE>(t, x, N, P, lane, ext);
+    for (int i = lane; i < NL; i += TPP) {
+      const int py = i % E, pz = i / E;
+      const long long row0 = xrow_offset(N, P, py, pz);
+      read_xline<T>(x, row0, xl);
+      const Sides<T> sd = xline_sides<T, MODE>(t, x, N, P, row0);
+      int base, stride;
+      line_geom(0, i, base, stride);
+      Line<T> a, b;
+      line_mass<T>(t, xl, a);
+      line_sipg<T, false>(t, xl, sd, b);
+      store_line(A, base, stride, a);
+      store_line(B, base, stride, b);
     }
   }
   __syncthreads();
   if constexpr (D == 3) {
-    // Y phase: c = M_y b + L_y a -> B, d = M_y a -> A; ext of z faces: M_y
-    for (int i = lane; active && i < NL + 4 * E; i += TPP) {
-      if (i < NL) {
-        int base, stride;
-        line_geom(1, i, base, stride);
-        Line<T> a, b, c, d;
-        load_line(bufA, base, stride, a);
-        load_line(bufB, base, stride, b);
-        line_mass<T>(t, b, c);
-        line_sipg<T, true>(t, a, ext[ext_idx(1, 0, 0, i)], ext[ext_idx(1, 0, 1, i)],
-                           ext[ext_idx(1, 1, 0, i)], ext[ext_idx(1, 1, 1, i)], c);
-        line_mass<T>(t, a, d);
-        store_line(bufB, base, stride, c);
-        store_line(bufA, base, stride, d);
-      } else {
-        ext_mass_line<T>(t, ext, 2, 0, i - NL);
+    // Y: c = M_y b + L_y a -> B, d = M_y a -> A; z-face data contracted along x
+    if (active) {
+      for (int i = lane; i < NL + 2 * NCOMP * E; i += TPP) {
+        if (i < NL) {
+          const int px = i % E, pz = i / E;
+          int base, stride;
+          line_geom(1, i, base, stride);
+          Line<T> a, b, c, d;
+          load_line(A, base, stride, a);
+          load_line(B, base, stride, b);
+          const Sides<T> sd = (MODE == 0) ? yline_sides<T, NCOMP>(t, ext, N, P, px, pz) : ysd_global;
+          line_mass<T>(t, b, c);
+          line_sipg<T, true>(t, a, sd, c);
+          line_mass<T>(t, a, d);
+          store_line(B, base, stride, c);
+          store_line(A, base, stride, d);
+        } else {
+          extz_mass_x_line<T, NCOMP>(t, ext, i - NL);
+        }
       }
     }
     __syncthreads();
-    // Z phase: y = M_z c + L_z d
-    for (int i = lane; active && i < NL; i += TPP) {
-      int base, stride;
-      line_geom(2, i, base, stride);
-      Line<T> c, d, y;
-      load_line(bufB, base, stride, c);
-      load_line(bufA, base, stride, d);
-      line_mass<T>(t, c, y);
-      line_sipg<T, true>(t, d, ext[ext_idx(2, 0, 0, i)], ext[ext_idx(2, 0, 1, i)],
-                         ext[ext_idx(2, 1, 0, i)], ext[ext_idx(2, 1, 1, i)], y);
-      emit(i, base, stride, y);
+    // Z: y = M_z c + L_z d
+    if (active) {
+      for (int i = lane; i < NL; i += TPP) {
+        const int px = i % E, py = i / E;
+        int base, stride;
+        line_geom(2, i, base, stride);
+        Line<T> c, d, y;
+        load_line(B, base, stride, c);
+        load_line(A, base, stride, d);
+        const Sides<T> sd = zline_sides<T, NCOMP>(t, ext, N, P, px, py);
+        line_mass<T>(t, c, y);
+        line_sipg<T, true>(t, d, sd, y);
+        emit(i, base, stride, y);
+      }
     }
   } else {
-    // Y phase (2-D): y = M_y b + L_y a
-    for (int i = lane; active && i < NL; i += TPP) {
-      int base, stride;
-      line_geom(1, i, base, stride);
-      Line<T> a, b, y;
-      load_line(bufA, base, stride, a);
-      load_line(bufB, base, stride, b);
-      line_mass<T>(t, b, y);
-      line_sipg<T, true>(t, a, ext[ext_idx(1, 0, 0, i)], ext[ext_idx(1, 0, 1, i)],
-                         ext[ext_idx(1, 1, 0, i)], ext[ext_idx(1, 1, 1, i)], y);
-      emit(i, base, stride, y);
+    // Y (2-D): y = M_y b + L_y a
+    if (active) {
+      for (int i = lane; i < NL; i += TPP) {
+        const int px = i;
+        int base, stride;
+        line_geom(1, i, base, stride);
+        Line<T> a, b, y;
+        load_line(A, base, stride, a);
+        load_line(B, base, stride, b);
+        const Sides<T> sd = (MODE == 0) ? yline_sides<T, NCOMP>(t, ext, N, P, px, 0) : ysd_global;
+        line_mass<T>(t, b, y);
+        line_sipg<T, true>(t, a, sd, y);
+        emit(i, base, stride, y);
+      }
     }
   }
 }
 
-// Coalesced write of the tile back to the patch's cells (y = tile, or
-// y += tile when ADD).
-template <typename T, bool ADD>
-__device__ __forceinline__ void store_tile(T* __restrict__ y, int N, const PatchPos& P, int lane,
-                                           const T* tile) {
-  for (int i = lane; i < NCP * NC; i += TPP) {
-    const int c = i / NC, loc = i % NC;
-    const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
-    const int ax = loc % n, ay = (loc / n) % n, az = loc / (n * n);
-    const long long cell = cell_index(N, P.lo[0] + cx, P.lo[1] + cy, (D == 3) ? P.lo[2] + cz : 0);
-    const T v = tile[toff(cx * n + ax, cy * n + ay, cz * n + az)];
-    if (ADD) y[cell * NC + loc] += v;
-    else y[cell * NC + loc] = v;
+// Load the last-direction line of b (z-line in 3-D, y-line in 2-D) at line l.
+template <typename T>
+__device__ __forceinline__ void read_lastline(const T* __restrict__ b, int N, const PatchPos& P, int l,
+                                              Line<T>& v) {
+  if constexpr (D == 3) {
+    const long long base = node_offset(N, P, l % E, l / E, 0);
+    const long long cz = (long long)N * N * NC;  // next cell in z
+#pragma unroll
+    for (int p = 0; p < E; ++p) v.v[p] = b[base + (p / n) * cz + (p % n) * (n * n)];
+  } else {
+    const long long base = node_offset(N, P, l, 0, 0);
+    const long long cy = (long long)N * NC;      // next cell in y
+#pragma unroll
+    for (int p = 0; p < E; ++p) v.v[p] = b[base + (p / n) * cy + (p % n) * n];
   }
 }
 
-template <int NB, bool EXT, typename T>
+template <int NB, int NEXTV>
 struct Smem {
-  static constexpr int per_patch = NB * TS + (EXT ? NEXT : 0);
+  static constexpr int per_patch = NB * TS + NEXTV;
 };
 
 // ---------------------------------------------------------------- apply
@@ -436,29 +598,40 @@ template <typename T, int PPB>
 __global__ void __launch_bounds__(TPP * PPB)
 k_apply(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
         T* __restrict__ y, long long ndof) {
-  constexpr int PP = Smem<2, true, T>::per_patch;
+  constexpr int PP = Smem<2, (D - 1) * 2 * 2 * NF>::per_patch;
   __shared__ T smem[PPB * PP];
   const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
-  const int pid = blockIdx.x * PPB + slot;
+  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
   const bool active = pid < g.npatch;
-  T* bufA = smem + slot * PP;
-  T* bufB = bufA + TS;
-  T* ext = bufB + TS;
+  T* A = smem + slot * PP;
+  T* B = A + TS;
+  T* ext = B + TS;
   const long long roff = (long long)blockIdx.y * ndof;
   const T* xr = x + roff;
   T* yr = y + roff;
-  PatchPos P = patch_pos(g, active ? pid : 0);
-  if (active) {
-    load_tile<T>(xr, g.N, P, lane, bufA);
-    load_ext<T, 0>(t, xr, g.N, P, lane, ext);
-  }
-  __syncthreads();
-  operator_passes<T>(t, bufA, bufB, ext, lane, active, [&](int, int base, int stride, const Line<T>& v) {
+  const PatchPos P = patch_pos(g, active ? pid : 0);
+  Line<T> xl;
+  Sides<T> ysd{};
+  operator_passes<T, 0>(t, xr, g.N, P, A, B, ext, lane, active, xl, ysd,
+                        [&](int, int base, int stride, const Line<T>& v) {
 #pragma unroll
-    for (int p = 0; p < E; ++p) bufA[base + p * stride] = scale * v.v[p];
-  });
+                          for (int p = 0; p < E; ++p) A[base + p * stride] = scale * v.v[p];
+                        });
   __syncthreads();
-  if (active) store_tile<T, false>(yr, g.N, P, lane, bufA);
+  // X2: contiguous row stores
+  if (active) {
+    for (int i = lane; i < NL; i += TPP) {
+      const int py = i % E, pz = i / E;
+      int base, stride;
+      line_geom(0, i, base, stride);
+      const long long row0 = xrow_offset(g.N, P, py, pz);
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        yr[row0 + a] = A[base + a];
+        yr[row0 + NC + a] = A[base + n + a];
+      }
+    }
+  }
 }
 
 // ----------------------------------------------------------------- mass
@@ -468,15 +641,25 @@ k_mass(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restric
        T* __restrict__ y, long long ndof) {
   __shared__ T smem[PPB * TS];
   const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
-  const int pid = blockIdx.x * PPB + slot;
+  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
   const bool active = pid < g.npatch;
   T* tile = smem + slot * TS;
   const long long roff = (long long)blockIdx.y * ndof;
-  PatchPos P = patch_pos(g, active ? pid : 0);
-  if (active) load_tile<T>(x + roff, g.N, P, lane, tile);
+  const PatchPos P = patch_pos(g, active ? pid : 0);
+  if (active) {
+    for (int i = lane; i < NL; i += TPP) {
+      const int py = i % E, pz = i / E;
+      int base, stride;
+      line_geom(0, i, base, stride);
+      Line<T> v, o;
+      read_xline<T>(x + roff, xrow_offset(g.N, P, py, pz), v);
+      line_mass<T>(t, v, o);
+      store_line(tile, base, stride, o);
+    }
+  }
   __syncthreads();
 #pragma unroll
-  for (int dir = 0; dir < D; ++dir) {
+  for (int dir = 1; dir < D; ++dir) {
     if (active) {
       for (int i = lane; i < NL; i += TPP) {
         int base, stride;
@@ -484,16 +667,24 @@ k_mass(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restric
         Line<T> v, o;
         load_line(tile, base, stride, v);
         line_mass<T>(t, v, o);
-        if (dir == D - 1) {
-#pragma unroll
-          for (int p = 0; p < E; ++p) o.v[p] *= scale;
-        }
         store_line(tile, base, stride, o);
       }
     }
     __syncthreads();
   }
-  if (active) store_tile<T, false>(y + roff, g.N, P, lane, tile);
+  if (active) {
+    for (int i = lane; i < NL; i += TPP) {
+      const int py = i % E, pz = i / E;
+      int base, stride;
+      line_geom(0, i, base, stride);
+      const long long row0 = xrow_offset(g.N, P, py, pz);
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        y[roff + row0 + a] = scale * tile[base + a];
+        y[roff + row0 + NC + a] = scale * tile[base + n + a];
+      }
+    }
+  }
 }
 
 // -------------------------------------------------------------- smoother
@@ -503,94 +694,133 @@ template <typename T, int PPB, int MODE>
 __global__ void __launch_bounds__(TPP * PPB)
 k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale, T* __restrict__ x,
          const T* __restrict__ b, long long ndof) {
-  constexpr int PP = Smem<3, true, T>::per_patch;
+  constexpr int PP = Smem<2, (D - 2) * 2 * NF>::per_patch;  // z-face traces only
   __shared__ T smem[PPB * PP];
   const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
-  const int pid = blockIdx.x * PPB + slot;
+  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
   const bool active = pid < g.npatch;
-  T* bufA = smem + slot * PP;
-  T* bufB = bufA + TS;
-  T* bufC = bufB + TS;
-  T* ext = bufC + TS;
+  T* A = smem + slot * PP;
+  T* B = A + TS;
+  T* ext = B + TS;
   const long long roff = (long long)blockIdx.y * ndof;
   T* xr = x + roff;
   const T* br = b + roff;
-  PatchPos P = patch_pos(g, active ? pid : 0);
-  if (active) {
-    load_tile<T>(xr, g.N, P, lane, bufA);
-    load_tile<T>(br, g.N, P, lane, bufC);
-    load_ext<T, MODE>(t, xr, g.N, P, lane, ext);
-  }
-  __syncthreads();
+  const PatchPos P = patch_pos(g, active ? pid : 0);
   const int tyx = P.ty[0], tyy = P.ty[1], tyz = P.ty[2];
-  // residual lines of the last operator pass, contracted with S^T of that
-  // direction and parked in A
-  auto emit = [&](int, int base, int stride, const Line<T>& v) {
-    Line<T> r, o;
+  Line<T> xl;  // the thread's x-line of x, kept for the final update
+  // y-face couplings of the thread's y-line, read early from global
+  const Sides<T> ysd = active ? yline_sides_global<T, MODE>(t, xr, g.N, P, lane % E, lane / E)
+                              : Sides<T>{};
+
+  // residual r = b - A x on the last pass, contracted with S^T of that direction
+  operator_passes<T, MODE>(t, xr, g.N, P, A, B, ext, lane, active, xl, ysd,
+                           [&](int l, int base, int stride, const Line<T>& v) {
+                             Line<T> r, o;
+                             read_lastline<T>(br, g.N, P, l, r);
 #pragma unroll
-    for (int p = 0; p < E; ++p) r.v[p] = bufC[base + p * stride] - scale * v.v[p];
-    line_St<T>(t, (D == 3) ? tyz : tyy, r, o);
-    store_line(bufA, base, stride, o);
-  };
-  operator_passes<T>(t, bufA, bufB, ext, lane, active, emit);
+                             for (int p = 0; p < E; ++p) r.v[p] -= scale * v.v[p];
+                             line_St<T>(t, (D == 3) ? tyz : tyy, r, o);
+                             store_line(A, base, stride, o);
+                           });
   __syncthreads();
   if constexpr (D == 3) {
-    // S_y^T
+    // X1: S_x^T
+    if (active)
+      for (int i = lane; i < NL; i += TPP) {
+        int base, stride;
+        line_geom(0, i, base, stride);
+        Line<T> v, o;
+        load_line(A, base, stride, v);
+        line_St<T>(t, tyx, v, o);
+        store_line(A, base, stride, o);
+      }
+    __syncthreads();
+    // Y1: S_y^T, scale by 1/(sum lambda), S_y
+    if (active)
+      for (int i = lane; i < NL; i += TPP) {
+        const int qx = i % E, qz = i / E;
+        int base, stride;
+        line_geom(1, i, base, stride);
+        const T lt = t->lam[tyx][qx] + t->lam[tyz][qz];
+        Line<T> v, o;
+        load_line(A, base, stride, v);
+        line_St<T>(t, tyy, v, o);
+#pragma unroll
+        for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(t->lam[tyy][q] + lt));
+        line_S<T>(t, tyy, o, v);
+        store_line(A, base, stride, v);
+      }
+    __syncthreads();
+    // Z1: S_z
+    if (active)
+      for (int i = lane; i < NL; i += TPP) {
+        int base, stride;
+        line_geom(2, i, base, stride);
+        Line<T> v, o;
+        load_line(A, base, stride, v);
+        line_S<T>(t, tyz, v, o);
+        store_line(A, base, stride, o);
+      }
+    __syncthreads();
+  } else {
+    // X1: S_x^T, scale, S_x
+    if (active)
+      for (int i = lane; i < NL; i += TPP) {
+        const int qy = i;
+        int base, stride;
+        line_geom(0, i, base, stride);
+        const T lt = t->lam[tyy][qy];
+        Line<T> v, o;
+        load_line(A, base, stride, v);
+        line_St<T>(t, tyx, v, o);
+#pragma unroll
+        for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(t->lam[tyx][q] + lt));
+        line_S<T>(t, tyx, o, v);
+        store_line(A, base, stride, v);
+      }
+    __syncthreads();
+    // Y1: S_y
     if (active)
       for (int i = lane; i < NL; i += TPP) {
         int base, stride;
         line_geom(1, i, base, stride);
         Line<T> v, o;
-        load_line(bufA, base, stride, v);
-        line_St<T>(t, tyy, v, o);
-        store_line(bufA, base, stride, o);
+        load_line(A, base, stride, v);
+        line_S<T>(t, tyy, v, o);
+        store_line(A, base, stride, o);
       }
     __syncthreads();
   }
-  // S_x^T, scale by 1/(sum lambda), S_x
-  if (active)
+  // X2 (3-D) / final x pass (2-D): x += S_x delta on the kept nodes, or, in
+  // 3-D, x += delta with delta already in physical coordinates along x.
+  if (active) {
     for (int i = lane; i < NL; i += TPP) {
+      const int py = i % E, pz = i / E;
+      const bool keep_line = (py > 0 || (tyy & 1)) && (py < E - 1 || (tyy & 2)) &&
+                             (D == 2 || ((pz > 0 || (tyz & 1)) && (pz < E - 1 || (tyz & 2))));
+      if (!keep_line) continue;
       int base, stride;
       line_geom(0, i, base, stride);
-      const int qy = i % E, qz = i / E;
-      T lt = t->lam[tyy][qy];
-      if (D == 3) lt += t->lam[tyz][qz];
-      Line<T> v, o;
-      load_line(bufA, base, stride, v);
-      line_St<T>(t, tyx, v, o);
-#pragma unroll
-      for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale / (t->lam[tyx][q] + lt));
-      line_S<T>(t, tyx, o, v);
-      store_line(bufA, base, stride, v);
-    }
-  __syncthreads();
-  // S_y (and S_z)
-#pragma unroll
-  for (int dir = 1; dir < D; ++dir) {
-    if (active)
-      for (int i = lane; i < NL; i += TPP) {
-        int base, stride;
-        line_geom(dir, i, base, stride);
-        Line<T> v, o;
-        load_line(bufA, base, stride, v);
-        line_S<T>(t, dir == 1 ? tyy : tyz, v, o);
-        store_line(bufA, base, stride, o);
+      Line<T> dl;
+      load_line(A, base, stride, dl);
+      if constexpr (D == 3) {
+        Line<T> o;
+        line_S<T>(t, tyx, dl, o);
+        dl = o;
       }
-    __syncthreads();
-  }
-  // x += delta on V_j (dropped nodes have zero rows in S, so delta = 0 there;
-  // they are skipped to leave other patches' reads untouched)
-  if (active) {
-    for (int i = lane; i < NCP * NC; i += TPP) {
-      const int c = i / NC, loc = i % NC;
-      const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
-      const int px = cx * n + loc % n, py = cy * n + (loc / n) % n, pz = cz * n + loc / (n * n);
-      const bool keep = (px > 0 || (tyx & 1)) && (px < E - 1 || (tyx & 2)) &&
-                        (py > 0 || (tyy & 1)) && (py < E - 1 || (tyy & 2)) &&
-                        (D == 2 || ((pz > 0 || (tyz & 1)) && (pz < E - 1 || (tyz & 2))));
-      if (keep) {
-        const long long cell = cell_index(g.N, P.lo[0] + cx, P.lo[1] + cy, (D == 3) ? P.lo[2] + cz : 0);
-        xr[cell * NC + loc] += bufA[toff(px, py, pz)];
+      // whole rows: the dropped end nodes of V_j are rewritten with their
+      // unchanged value (delta is exactly zero there), so no same-colour
+      // reader can observe a different value
+      const long long row0 = xrow_offset(g.N, P, py, pz);
+      Line<T> nx;
+#pragma unroll
+      for (int p = 0; p < E; ++p) nx.v[p] = xl.v[p] + dl.v[p];
+      if (!(tyx & 1)) nx.v[0] = xl.v[0];
+      if (!(tyx & 2)) nx.v[E - 1] = xl.v[E - 1];
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        xr[row0 + a] = nx.v[a];
+        xr[row0 + NC + a] = nx.v[n + a];
       }
     }
   }
@@ -598,72 +828,72 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale, T* 
 
 // ------------------------------------------------- residual + restriction
 // bc = P^T (b - A x): the colour-0 patch of level l is the set of children of
-// one coarse cell, so its tile residual contracts with the stacked P^T per
+// one coarse cell, so its residual contracts with the stacked P^T per
 // direction straight into that coarse cell.
 template <typename T, int PPB>
 __global__ void __launch_bounds__(TPP * PPB)
 k_restrict(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
            const T* __restrict__ b, T* __restrict__ bc, long long ndof, long long ndof_c) {
-  constexpr int PP = Smem<3, true, T>::per_patch;
+  constexpr int PP = Smem<2, (D - 1) * 2 * 2 * NF>::per_patch;
   __shared__ T smem[PPB * PP];
   const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
-  const int pid = blockIdx.x * PPB + slot;
+  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
   const bool active = pid < g.npatch;
-  T* bufA = smem + slot * PP;
-  T* bufB = bufA + TS;
-  T* bufC = bufB + TS;
-  T* ext = bufC + TS;
+  T* A = smem + slot * PP;
+  T* B = A + TS;
+  T* ext = B + TS;
   const long long roff = (long long)blockIdx.y * ndof;
-  PatchPos P = patch_pos(g, active ? pid : 0);
-  if (active) {
-    load_tile<T>(x + roff, g.N, P, lane, bufA);
-    load_tile<T>(b + roff, g.N, P, lane, bufC);
-    load_ext<T, 0>(t, x + roff, g.N, P, lane, ext);
-  }
+  const PatchPos P = patch_pos(g, active ? pid : 0);
+  Line<T> xl;
+  Sides<T> ysd{};
+  operator_passes<T, 0>(t, x + roff, g.N, P, A, B, ext, lane, active, xl, ysd,
+                        [&](int l, int base, int stride, const Line<T>& v) {
+                          Line<T> r;
+                          read_lastline<T>(b + roff, g.N, P, l, r);
+#pragma unroll
+                          for (int nu = 0; nu < n; ++nu) {
+                            T s = T(0);
+#pragma unroll
+                            for (int p = 0; p < E; ++p) s += t->P[p * n + nu] * (r.v[p] - scale * v.v[p]);
+                            A[base + nu * stride] = s;
+                          }
+                        });
   __syncthreads();
-  auto emit = [&](int, int base, int stride, const Line<T>& v) {
-#pragma unroll
-    for (int nu = 0; nu < n; ++nu) {
-      T s = T(0);
-#pragma unroll
-      for (int p = 0; p < E; ++p) s += t->P[p * n + nu] * (bufC[base + p * stride] - scale * v.v[p]);
-      bufA[base + nu * stride] = s;
-    }
-  };
-  operator_passes<T>(t, bufA, bufB, ext, lane, active, emit);
-  __syncthreads();
-  // restrict along the remaining directions (y then x in 3-D; x in 2-D)
-#pragma unroll
-  for (int dir = D - 2; dir >= 0; --dir) {
-    if (active) {
-      // lines along dir whose coordinates in already-restricted directions are < n
-      const int nlines = (D == 3) ? (dir == 1 ? E * n : n * n) : n;
-      for (int i = lane; i < nlines; i += TPP) {
-        int base, stride;
-        if (D == 3) {
-          if (dir == 1) { const int px = i % E, pz = i / E; base = px + pz * SZ; stride = SY; }
-          else { const int py = i % n, pz = i / n; base = py * SY + pz * SZ; stride = 1; }
-        } else { base = i * SY; stride = 1; }
+  if constexpr (D == 3) {
+    // restrict along y: lines (px, pz < n)
+    if (active)
+      for (int i = lane; i < E * n; i += TPP) {
+        const int px = i % E, pz = i / E;
+        const int base = px + pz * SZ, stride = SY;
         Line<T> v;
-        load_line(bufA, base, stride, v);
+        load_line(A, base, stride, v);
 #pragma unroll
         for (int nu = 0; nu < n; ++nu) {
           T s = T(0);
 #pragma unroll
           for (int p = 0; p < E; ++p) s += t->P[p * n + nu] * v.v[p];
-          bufA[base + nu * stride] = s;
+          A[base + nu * stride] = s;
         }
       }
-    }
     __syncthreads();
   }
+  // restrict along x: lines (py < n, pz < n) into rows of the coarse cell
   if (active) {
     const int Nc = g.N / 2;
     const long long cell = cell_index(Nc, P.lo[0] / 2, P.lo[1] / 2, (D == 3) ? P.lo[2] / 2 : 0);
     T* out = bc + (long long)blockIdx.y * ndof_c + cell * NC;
-    for (int i = lane; i < NC; i += TPP) {
-      const int ax = i % n, ay = (i / n) % n, az = i / (n * n);
-      out[i] = bufA[toff(ax, ay, az)];
+    for (int i = lane; i < NC / n; i += TPP) {
+      const int py = i % n, pz = i / n;
+      const int base = py * SY + pz * SZ;
+      Line<T> v;
+      load_line(A, base, 1, v);
+#pragma unroll
+      for (int nu = 0; nu < n; ++nu) {
+        T s = T(0);
+#pragma unroll
+        for (int p = 0; p < E; ++p) s += t->P[p * n + nu] * v.v[p];
+        out[i * n + nu] = s;
+      }
     }
   }
 }
@@ -675,34 +905,41 @@ k_prolong(const Tab<K, T>* __restrict__ t, PatchGrid g, const T* __restrict__ xc
           T* __restrict__ x, long long ndof, long long ndof_c) {
   __shared__ T smem[PPB * TS];
   const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
-  const int pid = blockIdx.x * PPB + slot;
+  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
   const bool active = pid < g.npatch;
   T* tile = smem + slot * TS;
-  PatchPos P = patch_pos(g, active ? pid : 0);
+  const PatchPos P = patch_pos(g, active ? pid : 0);
+  const long long roff = (long long)blockIdx.y * ndof;
+  // along x: coarse rows (ly, lz) straight from global
   if (active) {
     const int Nc = g.N / 2;
     const long long cell = cell_index(Nc, P.lo[0] / 2, P.lo[1] / 2, (D == 3) ? P.lo[2] / 2 : 0);
     const T* in = xc + (long long)blockIdx.y * ndof_c + cell * NC;
-    for (int i = lane; i < NC; i += TPP) {
-      const int ax = i % n, ay = (i / n) % n, az = i / (n * n);
-      tile[toff(ax, ay, az)] = in[i];
+    for (int i = lane; i < NC / n; i += TPP) {
+      const int py = i % n, pz = i / n;
+      const int base = py * SY + pz * SZ;
+      T v[n];
+#pragma unroll
+      for (int nu = 0; nu < n; ++nu) v[nu] = in[i * n + nu];
+#pragma unroll
+      for (int p = 0; p < E; ++p) {
+        T s = T(0);
+#pragma unroll
+        for (int nu = 0; nu < n; ++nu) s += t->P[p * n + nu] * v[nu];
+        tile[base + p] = s;
+      }
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int dir = 0; dir < D; ++dir) {
+  for (int dir = 1; dir < D; ++dir) {
     if (active) {
       // lines along dir; coordinates in later directions still < n
-      const int nlines = (D == 3) ? (dir == 0 ? n * n : dir == 1 ? E * n : E * E) : (dir == 0 ? n : E);
-      for (int i = lane; i < nlines; i += TPP) {
+      const int nlines = (D == 3 && dir == 1) ? E * n : E * E;
+      for (int i = lane; i < (D == 2 ? E : nlines); i += TPP) {
         int base, stride;
-        if (D == 3) {
-          if (dir == 0) { const int py = i % n, pz = i / n; base = py * SY + pz * SZ; stride = 1; }
-          else if (dir == 1) { const int px = i % E, pz = i / E; base = px + pz * SZ; stride = SY; }
-          else { const int px = i % E, py = i / E; base = px + py * SY; stride = SZ; }
-        } else {
-          if (dir == 0) { base = i * SY; stride = 1; } else { base = i; stride = SY; }
-        }
+        if (D == 3 && dir == 1) { const int px = i % E, pz = i / E; base = px + pz * SZ; stride = SY; }
+        else line_geom(dir, i, base, stride);
         T v[n];
 #pragma unroll
         for (int nu = 0; nu < n; ++nu) v[nu] = tile[base + nu * stride];
@@ -717,7 +954,19 @@ k_prolong(const Tab<K, T>* __restrict__ t, PatchGrid g, const T* __restrict__ xc
     }
     __syncthreads();
   }
-  if (active) store_tile<T, true>(x + (long long)blockIdx.y * ndof, g.N, P, lane, tile);
+  if (active) {
+    for (int i = lane; i < NL; i += TPP) {
+      const int py = i % E, pz = i / E;
+      int base, stride;
+      line_geom(0, i, base, stride);
+      const long long row0 = roff + xrow_offset(g.N, P, py, pz);
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        x[row0 + a] += tile[base + a];
+        x[row0 + NC + a] += tile[base + n + a];
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------- coarse solve
@@ -732,38 +981,42 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
 #pragma unroll
   for (int i = 0; i < 3; ++i) { P.lo[i] = 0; P.ty[i] = 3; }
   const long long roff = (long long)blockIdx.y * ndof;
-  load_tile<T>(b + roff, 2, P, lane, tile);
+  // S_x^T straight from the rows of b
+  for (int i = lane; i < NL; i += TPP) {
+    const int py = i % E, pz = i / E;
+    int base, stride;
+    line_geom(0, i, base, stride);
+    Line<T> v, o;
+    read_xline<T>(b + roff, xrow_offset(2, P, py, pz), v);
+    line_St_t<T, 3>(t, v, o);
+    store_line(tile, base, stride, o);
+  }
   __syncthreads();
-  // S^T along z (3-D), y; then x with the eigenvalue scaling and S_x; then S_y, S_z
+  // S^T along the remaining directions; the last one also scales and applies S
 #pragma unroll
-  for (int dir = D - 1; dir >= 1; --dir) {
+  for (int dir = 1; dir < D; ++dir) {
     for (int i = lane; i < NL; i += TPP) {
       int base, stride;
       line_geom(dir, i, base, stride);
       Line<T> v, o;
       load_line(tile, base, stride, v);
       line_St_t<T, 3>(t, v, o);
+      if (dir == D - 1) {
+        const int qa = i % E, qb = i / E;
+        T lt = t->lam[3][qa];
+        if (D == 3) lt += t->lam[3][qb];
+#pragma unroll
+        for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(t->lam[3][q] + lt));
+        line_S_t<T, 3>(t, o, v);
+        o = v;
+      }
       store_line(tile, base, stride, o);
     }
     __syncthreads();
   }
-  for (int i = lane; i < NL; i += TPP) {
-    int base, stride;
-    line_geom(0, i, base, stride);
-    const int qy = i % E, qz = i / E;
-    T lt = t->lam[3][qy];
-    if (D == 3) lt += t->lam[3][qz];
-    Line<T> v, o;
-    load_line(tile, base, stride, v);
-    line_St_t<T, 3>(t, v, o);
+  // S along the directions before the last, ending with x as contiguous rows
 #pragma unroll
-    for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale / (t->lam[3][q] + lt));
-    line_S_t<T, 3>(t, o, v);
-    store_line(tile, base, stride, v);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int dir = 1; dir < D; ++dir) {
+  for (int dir = D - 2; dir >= 1; --dir) {
     for (int i = lane; i < NL; i += TPP) {
       int base, stride;
       line_geom(dir, i, base, stride);
@@ -774,7 +1027,20 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
     }
     __syncthreads();
   }
-  store_tile<T, false>(x + roff, 2, P, lane, tile);
+  for (int i = lane; i < NL; i += TPP) {
+    const int py = i % E, pz = i / E;
+    int base, stride;
+    line_geom(0, i, base, stride);
+    Line<T> v, o;
+    load_line(tile, base, stride, v);
+    line_S_t<T, 3>(t, v, o);
+    const long long row0 = roff + xrow_offset(2, P, py, pz);
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      x[row0 + a] = o.v[a];
+      x[row0 + NC + a] = o.v[n + a];
+    }
+  }
 }
 
 // ------------------------------------------------------------ launchers
