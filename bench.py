@@ -31,11 +31,16 @@ METRIC = "GDoF/s of SIPG apply & patch smoother; time-to-1e-10 solve, FP64 vs mi
 WORKLOAD = "poisson3d_q3_32c"
 
 
-def cpu_baseline(dim, k, L, sigma, b_host, iters_gpu, budget_iters=2):
+def cpu_baseline(dim, k, L, sigma, iters_gpu, budget_iters=2):
     """Time the oracle's own PCG (matrix-free Kronecker apply, FD smoother,
     V-cycle) on the host for a bounded number of iterations and scale to the
-    GPU's iteration count."""
+    GPU's iteration count.  The oracle builds its own load vector."""
     from oracle.multigrid import Hierarchy
+    from oracle.rhs import interpolate
+    from oracle.sipg import mass_operator
+    from paper_2405_18982_amd import inputs
+    N = 2 ** (L + 1)
+    b_host = mass_operator(dim, k, N) @ interpolate(dim, k, N, inputs.sine_load)
     try:
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
@@ -195,7 +200,7 @@ def main():
         "components": components,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(dim, k, L, sigma, b.cpu().numpy(), iters)
+        out["cpu_baseline"] = cpu_baseline(dim, k, L, sigma, iters)
     prob.close()
     print(json.dumps(out), flush=True)
 

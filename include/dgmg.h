@@ -88,6 +88,13 @@ dgmg_status dgmg_set_stream(dgmg_ctx* ctx, void* hip_stream);
  * enqueued afterwards. */
 dgmg_status dgmg_set_kappa(dgmg_ctx* ctx, double kappa);
 
+/* CG preconditioning by a captured HIP graph: on (default), dgmg_pcg_solve
+ * captures its V-cycle (CG residual -> CG direction workspace, for the
+ * given nrhs) on first use on a library-owned stream and replays it every
+ * iteration on the context stream; off, every kernel is launched from the
+ * host.  Both give bitwise identical results.  A new kappa drops the graphs. */
+dgmg_status dgmg_use_graphs(dgmg_ctx* ctx, int enable);
+
 /* Sizes: cells per direction and DoFs per right-hand side of a level. */
 long long dgmg_level_ndofs(const dgmg_ctx* ctx, int level);
 int dgmg_level_cells(const dgmg_ctx* ctx, int level);
@@ -171,6 +178,18 @@ dgmg_status dgmg_dot(dgmg_ctx* ctx, int level, const double* a, const double* b,
  * lam: host [2k+2] generalised eigenvalues, +inf in unused slots.  The
  * eigenvectors satisfy S^T M S = I on the kept nodes. */
 dgmg_status dgmg_patch_eigen(int degree, double sigma, int type, double* S, double* lam);
+
+/* Autotuner: for the finest level and nrhs right-hand sides, time every
+ * workgroup shape (patches per workgroup) and patch numbering (plain or
+ * XCD-aware) of apply_sipg and smooth_patch, in FP64 and, for a mixed-
+ * precision context, FP32, and use the fastest from then on.  Timings run on
+ * the CG workspace (its contents are overwritten; FP32 level vectors are
+ * allocated if missing).  cache_path (may be NULL) names a JSON file of
+ * earlier results keyed by architecture, dim, degree, levels, nrhs, precision
+ * and kernel; cached entries are used without timing and new ones appended.
+ * report (may be NULL): host buffer receiving one line per decision. */
+dgmg_status dgmg_autotune(dgmg_ctx* ctx, int nrhs, const char* cache_path, char* report,
+                          int report_len);
 
 const char* dgmg_last_error(const dgmg_ctx* ctx);
 dgmg_status dgmg_destroy(dgmg_ctx* ctx);

@@ -132,6 +132,20 @@ struct dgmg_ctx {
   int* active = nullptr;
   double* hbuf = nullptr;  // pinned host mirror of scalars
   int* hact = nullptr;
+  // V-cycle of the CG (r -> z) captured as a HIP graph, per nrhs; replayed on
+  // the caller's stream.  Captured on the library's own stream (default
+  // priority); invalidated when kappa changes.
+  bool use_graph = true;
+  // workgroup shape and XCD-aware numbering of the tuned kernels, per
+  // precision (0: FP64, 1: FP32); set by dgmg_autotune
+  struct Tuning {
+    int shape = 0;
+    int remap = 1;
+    double us = 0;
+  };
+  Tuning tune_apply[2], tune_smooth[2];
+  hipStream_t cap_stream = nullptr;
+  std::vector<hipGraphExec_t> vc_graph;  // index nrhs - 1
   std::string err;
 };
 
@@ -158,15 +172,15 @@ T* dalloc(long long count, hipError_t& e) {
   return e == hipSuccess ? (T*)p : nullptr;
 }
 
-// XCD-aware patch numbering (on unless DGMG_XCD_REMAP=0; the switch exists
-// to measure its effect).
-int xcd_remap_flag() {
-  static int flag = -1;
-  if (flag < 0) {
+// XCD-aware patch numbering: the tuned choice, unless DGMG_XCD_REMAP=0/1
+// forces it (used to measure its effect).
+int xcd_remap_flag(int tuned = 1) {
+  static int env = -2;
+  if (env == -2) {
     const char* e = std::getenv("DGMG_XCD_REMAP");
-    flag = (e && e[0] == '0') ? 0 : 1;
+    env = (e && (e[0] == '0' || e[0] == '1')) ? (e[0] - '0') : -1;
   }
-  return flag;
+  return env >= 0 ? env : tuned;
 }
 
 PatchGrid grid_colour0(const dgmg_ctx* c, int N) {
@@ -228,9 +242,15 @@ dgmg_status check_level(dgmg_ctx* c, int level, int lo, int nrhs) {
 
 // ------------------------------------------------------------ level ops
 template <typename T>
+constexpr int prec_index() { return sizeof(T) == 8 ? 0 : 1; }
+
+template <typename T>
 dgmg_status op_apply(dgmg_ctx* c, int l, const T* x, T* y, int nrhs) {
-  HIPCHK(c, kset<T>(c).apply(tab_of<T>(c), grid_colour0(c, c->lv[l].N), (T)level_scale(c, l), x, y,
-                             nrhs, c->lv[l].ndof, c->stream));
+  const auto& tu = c->tune_apply[prec_index<T>()];
+  PatchGrid g = grid_colour0(c, c->lv[l].N);
+  g.xcd_remap = xcd_remap_flag(tu.remap);
+  HIPCHK(c, kset<T>(c).apply[tu.shape](tab_of<T>(c), g, (T)level_scale(c, l), x, y, nrhs,
+                                       c->lv[l].ndof, c->stream));
   return DGMG_OK;
 }
 
@@ -242,8 +262,10 @@ dgmg_status op_smooth(dgmg_ctx* c, int l, T* x, const T* b, int reverse, int nrh
     const int col = reverse ? nc - 1 - i : i;
     PatchGrid g = grid_colour(c, c->lv[l].N, col);
     if (g.npatch == 0) continue;
-    HIPCHK(c, kset<T>(c).smooth(tab_of<T>(c), g, (T)sc, (T)(1.0 / sc), c->variant, x, b, nrhs,
-                                c->lv[l].ndof, c->stream));
+    const auto& tu = c->tune_smooth[prec_index<T>()];
+    g.xcd_remap = xcd_remap_flag(tu.remap);
+    HIPCHK(c, kset<T>(c).smooth[tu.shape](tab_of<T>(c), g, (T)sc, (T)(1.0 / sc), c->variant, x, b,
+                                          nrhs, c->lv[l].ndof, c->stream));
   }
   return DGMG_OK;
 }
@@ -344,6 +366,50 @@ dgmg_status precondition(dgmg_ctx* c, const double* r, double* z, int nrhs) {
   return DGMG_OK;
 }
 
+void drop_graphs(dgmg_ctx* c) {
+  for (hipGraphExec_t& g : c->vc_graph)
+    if (g) {
+      hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// z = V(r) for the CG: replay (capturing on first use) the graph of the
+// V-cycle on the CG workspace for this nrhs.
+dgmg_status precondition_cg(dgmg_ctx* c, int nrhs) {
+  if (!c->use_graph) return precondition(c, c->r, c->z, nrhs);
+  if ((int)c->vc_graph.size() < c->nrhs_max) c->vc_graph.resize(c->nrhs_max, nullptr);
+  hipGraphExec_t& ex = c->vc_graph[nrhs - 1];
+  if (!ex) {
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreate(&c->cap_stream));
+    // level buffers must exist before capture (allocation is not capturable)
+    if (c->prec == 64) RET(ensure_levels<double>(c, c->L - 1));
+    else RET(ensure_levels<float>(c, c->L));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    dgmg_status st = DGMG_OK;
+    if (e == hipSuccess) st = precondition(c, c->r, c->z, nrhs);
+    hipError_t e2 = (e == hipSuccess) ? hipStreamEndCapture(c->cap_stream, &graph) : e;
+    c->stream = user;
+    if (st != DGMG_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return st;
+    }
+    if (e2 != hipSuccess) return fail(c, DGMG_ERR_HIP, std::string("V-cycle capture: ") + hipGetErrorString(e2));
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      ex = nullptr;
+      return fail(c, DGMG_ERR_HIP, std::string("V-cycle graph instantiate: ") + hipGetErrorString(e));
+    }
+  }
+  HIPCHK(c, hipGraphLaunch(ex, c->stream));
+  return DGMG_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -429,9 +495,17 @@ DGMG_API dgmg_status dgmg_set_stream(dgmg_ctx* c, void* hip_stream) {
   return DGMG_OK;
 }
 
+DGMG_API dgmg_status dgmg_use_graphs(dgmg_ctx* c, int enable) {
+  if (!c) return DGMG_ERR_ARG;
+  c->use_graph = enable != 0;
+  if (!c->use_graph) drop_graphs(c);
+  return DGMG_OK;
+}
+
 DGMG_API dgmg_status dgmg_set_kappa(dgmg_ctx* c, double kappa) {
   if (!c) return DGMG_ERR_ARG;
   if (!(kappa > 0) || !std::isfinite(kappa)) return fail(c, DGMG_ERR_ARG, "kappa must be positive");
+  if (kappa != c->kappa) drop_graphs(c);  // level scales are baked into the graphs
   c->kappa = kappa;
   return DGMG_OK;
 }
@@ -593,7 +667,7 @@ DGMG_API dgmg_status dgmg_pcg_solve(dgmg_ctx* c, const double* b, double* x, int
   }
   if (!any) return DGMG_OK;
   HIPCHK(c, hipMemcpyAsync(c->active, c->hact, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-  RET(precondition(c, c->r, c->z, nrhs));
+  RET(precondition_cg(c, nrhs));
   HIPCHK(c, dgmg::blas_dot2(c->r, c->z, nullptr, nullptr, n, nrhs, c->partial, nullptr, rzb[0],
                             nullptr, s));
   HIPCHK(c, hipMemcpyAsync(c->p, c->z, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, s));
@@ -621,7 +695,7 @@ DGMG_API dgmg_status dgmg_pcg_solve(dgmg_ctx* c, const double* b, double* x, int
     }
     if (!any) { status = DGMG_OK; break; }
     HIPCHK(c, hipMemcpyAsync(c->active, c->hact, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-    RET(precondition(c, c->r, c->z, nrhs));
+    RET(precondition_cg(c, nrhs));
     HIPCHK(c, dgmg::blas_dot2(c->r, c->z, flexible ? c->z : nullptr, flexible ? c->q : nullptr, n,
                               nrhs, c->partial, c->partial2, rz_new, zq, s));
     HIPCHK(c, dgmg::blas_update_p(c->p, c->z, rz_new, rz_old, zq, alpha, c->active, flexible, n,
@@ -645,6 +719,161 @@ DGMG_API dgmg_status dgmg_dot(dgmg_ctx* c, int level, const double* a, const dou
   return DGMG_OK;
 }
 
+namespace {
+
+// ---------------------------------------------------------------- autotuner
+// Times every workgroup shape x XCD numbering of apply and smooth on the
+// finest level with HIP events (best of three batches) and keeps the fastest.
+// Results are cached in a JSON object, one entry per line:
+//   "gfx950/d3/k3/L4/nrhs16/fp64/smooth": {"shape": 0, "remap": 1, "us": 16.50},
+
+std::string tune_key(const dgmg_ctx* c, int nrhs, int prec, const char* kernel) {
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), "gfx950/d%d/k%d/L%d/nrhs%d/fp%d/%s", c->dim, c->k, c->L, nrhs, prec,
+                kernel);
+  return buf;
+}
+
+struct CacheEntry {
+  std::string key;
+  int shape, remap;
+  double us;
+};
+
+std::vector<CacheEntry> read_cache(const char* path) {
+  std::vector<CacheEntry> out;
+  if (!path) return out;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return out;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    char key[256];
+    CacheEntry e;
+    if (std::sscanf(line, " \"%255[^\"]\": {\"shape\": %d, \"remap\": %d, \"us\": %lf", key, &e.shape,
+                    &e.remap, &e.us) == 4) {
+      e.key = key;
+      out.push_back(e);
+    }
+  }
+  std::fclose(f);
+  return out;
+}
+
+void write_cache(const char* path, const std::vector<CacheEntry>& es) {
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  for (size_t i = 0; i < es.size(); ++i)
+    std::fprintf(f, "  \"%s\": {\"shape\": %d, \"remap\": %d, \"us\": %.3f}%s\n", es[i].key.c_str(),
+                 es[i].shape, es[i].remap, es[i].us, i + 1 < es.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
+template <typename T>
+dgmg_status tune_kernel(dgmg_ctx* c, int nrhs, bool smooth, T* x, T* y, double* best_us,
+                        dgmg_ctx::Tuning& out) {
+  auto& slot = smooth ? c->tune_smooth[prec_index<T>()] : c->tune_apply[prec_index<T>()];
+  const int L = c->L;
+  const int reps = smooth ? 3 : 20;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  double best = 1e300;
+  dgmg_ctx::Tuning pick = slot;
+  for (int shape = 0; shape < dgmg::kNumShapes; ++shape)
+    for (int remap = 0; remap < 2; ++remap) {
+      slot.shape = shape;
+      slot.remap = remap;
+      double t_best = 1e300;
+      for (int trial = 0; trial < 4; ++trial) {  // trial 0 warms up
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r) {
+          if (smooth) RET(op_smooth<T>(c, L, x, y, 0, nrhs));
+          else RET(op_apply<T>(c, L, x, y, nrhs));
+        }
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1e3 * ms / reps;
+        if (trial > 0 && us < t_best) t_best = us;
+      }
+      if (t_best < best) {
+        best = t_best;
+        pick.shape = shape;
+        pick.remap = remap;
+        pick.us = t_best;
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  slot = pick;
+  out = pick;
+  *best_us = best;
+  return DGMG_OK;
+}
+
+}  // namespace
+
+DGMG_API dgmg_status dgmg_autotune(dgmg_ctx* c, int nrhs, const char* cache_path, char* report,
+                                   int report_len) {
+  RET(check_level(c, c ? c->L : 0, 0, nrhs));
+  std::vector<CacheEntry> cache = read_cache(cache_path);
+  std::string rep;
+  bool dirty = false;
+  const int precs[2] = {64, 32};
+  for (int pi = 0; pi < 2; ++pi) {
+    if (precs[pi] == 32 && c->prec != 32) continue;
+    for (int kk = 0; kk < 2; ++kk) {
+      const bool smooth = kk == 1;
+      const std::string key = tune_key(c, nrhs, precs[pi], smooth ? "smooth" : "apply");
+      dgmg_ctx::Tuning tu;
+      bool found = false;
+      for (const CacheEntry& e : cache)
+        if (e.key == key && e.shape >= 0 && e.shape < dgmg::kNumShapes && (e.remap == 0 || e.remap == 1)) {
+          tu.shape = e.shape;
+          tu.remap = e.remap;
+          tu.us = e.us;
+          found = true;
+        }
+      if (!found) {
+        double us = 0;
+        const long long n = c->lv[c->L].ndof * nrhs;
+        if (pi == 0) {
+          RET(zero_vec<double>(c, c->p, n));
+          RET(zero_vec<double>(c, c->r, n));
+          RET(tune_kernel<double>(c, nrhs, smooth, c->p, smooth ? c->r : c->q, &us, tu));
+        } else {
+          RET(ensure_levels<float>(c, c->L));
+          Level& T = c->lv[c->L];
+          RET(zero_vec<float>(c, T.x32, n));
+          RET(zero_vec<float>(c, T.b32, n));
+          RET(tune_kernel<float>(c, nrhs, smooth, T.x32, T.b32, &us, tu));
+        }
+        cache.push_back({key, tu.shape, tu.remap, tu.us});
+        dirty = true;
+      }
+      auto& slot = smooth ? c->tune_smooth[pi] : c->tune_apply[pi];
+      slot = tu;
+      char line[256];
+      std::snprintf(line, sizeof(line), "%s shape=%d remap=%d us=%.3f%s\n", key.c_str(), tu.shape,
+                    tu.remap, tu.us, found ? " (cached)" : "");
+      rep += line;
+    }
+  }
+  if (dirty) write_cache(cache_path, cache);
+  drop_graphs(c);  // graphs hold the previous launch shapes
+  if (report && report_len > 0) {
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return DGMG_OK;
+}
+
 DGMG_API dgmg_status dgmg_patch_eigen(int degree, double sigma, int type, double* S, double* lam) {
   if (degree < 1 || degree > dgmg::kMaxDegree || !(sigma > 0) || type < 0 || type > 3 || !S || !lam)
     return DGMG_ERR_ARG;
@@ -663,6 +892,8 @@ DGMG_API const char* dgmg_last_error(const dgmg_ctx* c) {
 DGMG_API dgmg_status dgmg_destroy(dgmg_ctx* c) {
   if (!c) return DGMG_ERR_ARG;
   if (c->ready) hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   for (Level& L : c->lv) {
     hipFree(L.b64);
     hipFree(L.x64);

@@ -1044,10 +1044,19 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
 }
 
 // ------------------------------------------------------------ launchers
-template <typename T>
+// Workgroup shapes the autotuner chooses between: PPB_DEFAULT patches per
+// workgroup (variant 0) or twice as many (variant 1) while the workgroup stays
+// within 256 threads (larger patches keep one per workgroup).
+template <int V>
+struct Shape {
+  static constexpr int PPB =
+      (V == 1 && TPP * PPB_DEFAULT * 2 > 256) ? PPB_DEFAULT : PPB_DEFAULT * (V + 1);
+};
+
+template <typename T, int V>
 hipError_t launch_apply(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
                         long long ndof, hipStream_t s) {
-  constexpr int PPB = PPB_DEFAULT;
+  constexpr int PPB = Shape<V>::PPB;
   dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
   hipLaunchKernelGGL((k_apply<T, PPB>), grid, dim3(TPP * PPB), 0, s,
                      (const Tab<K, T>*)tab, g, scale, x, y, ndof);
@@ -1062,10 +1071,10 @@ hipError_t launch_mass(const void* tab, PatchGrid g, T scale, const T* x, T* y, 
                      (const Tab<K, T>*)tab, g, scale, x, y, ndof);
   return hipGetLastError();
 }
-template <typename T>
+template <typename T, int V>
 hipError_t launch_smooth(const void* tab, PatchGrid g, T scale, T inv_scale, int local_variant,
                          T* x, const T* b, int nrhs, long long ndof, hipStream_t s) {
-  constexpr int PPB = PPB_DEFAULT;
+  constexpr int PPB = Shape<V>::PPB;
   dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
   if (local_variant)
     hipLaunchKernelGGL((k_smooth<T, PPB, 2>), grid, dim3(TPP * PPB), 0, s,
@@ -1105,9 +1114,11 @@ hipError_t launch_coarse(const void* tab, T inv_scale, const T* b, T* x, int nrh
 template <typename T>
 KernelSet<T> make_set() {
   KernelSet<T> k;
-  k.apply = &launch_apply<T>;
+  k.apply[0] = &launch_apply<T, 0>;
+  k.apply[1] = &launch_apply<T, 1>;
   k.mass = &launch_mass<T>;
-  k.smooth = &launch_smooth<T>;
+  k.smooth[0] = &launch_smooth<T, 0>;
+  k.smooth[1] = &launch_smooth<T, 1>;
   k.restrict_residual = &launch_restrict<T>;
   k.prolongate_add = &launch_prolong<T>;
   k.coarse = &launch_coarse<T>;

@@ -29,6 +29,7 @@ SIGNATURES = {
     "dgmg_setup_levels": (_I, [_P, _I, _I, _I, _P]),
     "dgmg_set_stream": (_I, [_P, _P]),
     "dgmg_set_kappa": (_I, [_P, _D]),
+    "dgmg_use_graphs": (_I, [_P, _I]),
     "dgmg_level_ndofs": (_LL, [_P, _I]),
     "dgmg_level_cells": (_I, [_P, _I]),
     "dgmg_finest_level": (_I, [_P]),
@@ -48,6 +49,7 @@ SIGNATURES = {
     "dgmg_vcycle_f32": (_I, [_P, _P, _P, _I]),
     "dgmg_pcg_solve": (_I, [_P, _P, _P, _I, _D, _I, _I, _P, _P]),
     "dgmg_dot": (_I, [_P, _I, _P, _P, _I, _P]),
+    "dgmg_autotune": (_I, [_P, _I, _c.c_char_p, _P, _I]),
     "dgmg_patch_eigen": (_I, [_I, _D, _I, _P, _P]),
     "dgmg_last_error": (_c.c_char_p, [_P]),
     "dgmg_destroy": (_I, [_P]),
@@ -162,6 +164,18 @@ class Problem:
         out = np.zeros(self.ndofs(level) * self.dim)
         self._check(lib().dgmg_node_coords(self._ctx, level, out.ctypes.data))
         return out.reshape(-1, self.dim)
+
+    def autotune(self, nrhs=1, cache=None):
+        """Pick the fastest workgroup shapes of apply/smooth (finest level);
+        returns the decisions as text.  cache: JSON file path or None."""
+        buf = ctypes.create_string_buffer(4096)
+        self._sync_stream()
+        path = cache.encode() if cache else None
+        self._check(lib().dgmg_autotune(self._ctx, int(nrhs), path, buf, len(buf)))
+        return buf.value.decode()
+
+    def use_graphs(self, enable=True):
+        self._check(lib().dgmg_use_graphs(self._ctx, int(bool(enable))))
 
     def set_kappa(self, kappa):
         self.kappa = float(kappa)

@@ -1,0 +1,82 @@
+"""The autotuner's choices are all correct: every workgroup shape and patch
+numbering it can pick is forced through its JSON cache and checked against
+the oracle; tuning writes the cache and a second call reads it back."""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.sipg import kron_operator
+from oracle.smoother import FDSmoother
+from paper_2405_18982_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_18982_amd import dgmg  # noqa: E402
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def force_cache(path, dim, k, L, nrhs, shape, remap):
+    lines = []
+    for kern in ("apply", "smooth"):
+        key = f"gfx950/d{dim}/k{k}/L{L}/nrhs{nrhs}/fp64/{kern}"
+        lines.append(f'  "{key}": {{"shape": {shape}, "remap": {remap}, "us": 1.000}}')
+    path.write_text("{\n" + ",\n".join(lines) + "\n}\n")
+
+
+@pytest.mark.parametrize("dim,k,L", [(2, 2, 3), (2, 5, 2), (3, 1, 2), (3, 2, 2), (3, 3, 2), (3, 4, 1)])
+@pytest.mark.parametrize("shape,remap", list(itertools.product([0, 1], [0, 1])))
+def test_every_tunable_shape_matches_oracle(tmp_path, dim, k, L, shape, remap):
+    note(f"tuned shape={shape} remap={remap} d={dim} k={k} L={L}")
+    nrhs = 2
+    prob = dgmg.Problem(dim, k, L, nrhs_max=nrhs)
+    cache = tmp_path / "tune.json"
+    force_cache(cache, dim, k, L, nrhs, shape, remap)
+    rep = prob.autotune(nrhs=nrhs, cache=str(cache))
+    assert rep.count("(cached)") == 2 and f"shape={shape} remap={remap}" in rep
+    N = 2 ** (L + 1)
+    sig = inputs.sigma_of(k)
+    X = inputs.uniform(41, (nrhs, prob.ndofs()))
+    B = inputs.uniform(42, (nrhs, prob.ndofs()))
+    Y = prob.apply(torch.from_numpy(X).cuda()).cpu().numpy()
+    A = kron_operator(dim, k, N, sig)
+    Xg = torch.from_numpy(X).cuda()
+    prob.smooth(Xg, torch.from_numpy(B).cuda())
+    S = Xg.cpu().numpy()
+    fs = FDSmoother(dim, k, N, sig)
+    for j in range(nrhs):
+        assert rel(Y[j], A @ X[j]) <= 1e-12
+        assert rel(S[j], fs.step(X[j], B[j], list(range(2 ** dim)))) <= 1e-12
+    prob.close()
+
+
+def test_tuning_writes_and_reads_cache(tmp_path):
+    note("autotune run + cache")
+    prob = dgmg.Problem(3, 3, 3, precision=32, nrhs_max=4)
+    cache = tmp_path / "tune.json"
+    rep1 = prob.autotune(nrhs=4, cache=str(cache))
+    assert len(rep1.strip().splitlines()) == 4 and "(cached)" not in rep1
+    txt = cache.read_text()
+    assert txt.startswith("{") and txt.count('"shape"') == 4
+    rep2 = prob.autotune(nrhs=4, cache=str(cache))
+    assert rep2.count("(cached)") == 4
+    strip = [ln.replace(" (cached)", "") for ln in rep2.strip().splitlines()]
+    assert strip == rep1.strip().splitlines()
+    # the tuned context still solves to tolerance
+    B = torch.from_numpy(inputs.normal(43, (4, prob.ndofs()))).cuda()
+    x, it, relres = prob.solve(B, rtol=1e-10)
+    assert np.all(relres <= 1e-10) and np.all(it <= 15)
+    prob.close()

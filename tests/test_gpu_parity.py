@@ -9,6 +9,7 @@ import pytest
 
 from oracle.multigrid import Hierarchy
 from oracle.fdsolve import GlobalFD
+from oracle.rhs import interpolate
 from oracle.sipg import KronApply, kron_operator, mass_operator
 from oracle.smoother import FDSmoother
 from oracle.transfer import prolongation
@@ -50,6 +51,12 @@ def cuda(a, dtype=torch.float64):
 def host(t):
     torch.cuda.synchronize()
     return t.detach().cpu().numpy().astype(np.float64)
+
+
+def oracle_load(dim, k, N):
+    """Interpolated sine load b = M I_h f built by the oracle (an input to
+    both sides; never taken from the library)."""
+    return mass_operator(dim, k, N) @ interpolate(dim, k, N, inputs.sine_load)
 
 
 def close(got, ref, rtol=1e-12, mtol=1e-11):
@@ -194,9 +201,8 @@ def test_pcg_fp64(dim, k, L):
     prob = problem(dim, k, L)
     N = 2 ** (L + 1)
     sig = inputs.sigma_of(k)
-    b = prob.mass(cuda(inputs.sine_load(prob.node_coords())))
-    B = host(b)
-    x, it, rel = prob.solve(b, rtol=1e-10)
+    B = oracle_load(dim, k, N)
+    x, it, rel = prob.solve(cuda(B), rtol=1e-10)
     X = host(x)
     ap = KronApply(dim, k, N, sig)
     true_rel = np.linalg.norm(B - ap(X)) / np.linalg.norm(B)
@@ -287,9 +293,33 @@ def test_full_size_poisson3d_q3_32c():
     Xg = cuda(X)
     prob.smooth(Xg, cuda(B))
     close(host(Xg), FDSmoother(dim, k, N, sig).step(X, B, list(range(8))))
-    b = prob.mass(cuda(inputs.sine_load(prob.node_coords())))
-    x, it, rel = prob.solve(b, rtol=1e-10)
-    Bh = host(b)
+    Bh = oracle_load(dim, k, N)
+    x, it, rel = prob.solve(cuda(Bh), rtol=1e-10)
     u = GlobalFD(dim, k, N, sig).solve(Bh)
     assert np.linalg.norm(host(x) - u) <= 1e-8 * np.linalg.norm(u)
     assert it[0] <= 12
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_graph_replays_equal_eager(precision):
+    note(f"graph replay precision={precision}")
+    prob = dgmg.Problem(3, 2, 2, precision=precision, nrhs_max=3)
+    B = cuda(inputs.uniform(31, (3, prob.ndofs())))
+    y = torch.empty_like(B[0])
+    for kappa in (1.0, 2.5):
+        prob.set_kappa(kappa)
+        prob.use_graphs(False)
+        x_e, it_e, _ = prob.solve(B, rtol=1e-10)
+        x_e = x_e.clone()
+        x1, it1, _ = prob.solve(B[1].contiguous(), rtol=1e-10)
+        x1 = x1.clone()
+        prob.use_graphs(True)
+        for rep in range(3):
+            x_g, it_g, _ = prob.solve(B, rtol=1e-10)
+            assert torch.equal(x_g, x_e), (kappa, rep)
+            assert list(it_g) == list(it_e)
+            xs, _, _ = prob.solve(B[1].contiguous(), rtol=1e-10)  # second graph (nrhs = 1)
+            assert torch.equal(xs, x1)
+            prob.apply(B[rep].contiguous(), out=y)  # eager work between replays
+            torch.cuda.synchronize()
+    prob.close()
