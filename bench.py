@@ -11,8 +11,10 @@ V-cycle, PCG) with inputs resident in HBM.  `value` is solved DoFs per second
 Also reported: apply and smoothing-step throughput (GDoF/s) measured with HIP
 events on the library's stream, the mixed-precision (FP32 V-cycle) solve on
 the same problem, the roofline position of the dominant kernel (the patch
-smoother on the finest level), and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+smoother on the finest level), time to solution of the 3-D Q7 64^3 problem
+(134M DoFs) all-FP64 vs mixed and of 16 batched right-hand sides (3-D Q4 32^3)
+vs 16 single FP64 solves, and the FP64 CPU oracle timed on a bounded sample of
+the bench workload.  Kernel workgroup shapes are autotuned before timing.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
 """
@@ -28,6 +30,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GDoF/s of SIPG apply & patch smoother; time-to-1e-10 solve, FP64 vs mixed"
+CAL_BYTES = 32 * 1024 * 1024
+KERNEL_SRC = os.path.join(ROOT, "paper_2405_18982_amd", "csrc", "dgmg_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_smooth_poisson3d_q3_32c_traffic.txt")
+
+
+def traffic_from_profile():
+    """HBM bytes per finest-level smoother launch from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            key, val = line.split(":", 1)
+            vals[key.strip()] = val.strip()
+    if vals.get("kernel_source_sha256") != src:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 WORKLOAD = "poisson3d_q3_32c"
 
 
@@ -80,6 +105,74 @@ def cpu_baseline(dim, k, L, sigma, iters_gpu, budget_iters=2):
     }
 
 
+def _time_solves(prob, b, reps, warm=1):
+    import torch
+    x = torch.empty_like(b)
+    for _ in range(warm):
+        prob.solve(b, rtol=1e-10, maxit=100, out=x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, it, rel = prob.solve(b, rtol=1e-10, maxit=100, out=x)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, it, rel, x
+
+
+def bench_q7_mixed(reps=2):
+    """3-D Q7 64^3 (134M DoFs), b ~ U[-1,1] seed 3: all-FP64 solve vs FP32
+    V-cycle inside FP64 CG, same GPU, time to 1e-10."""
+    import torch
+    from paper_2405_18982_amd import dgmg, inputs
+    w = inputs.WORKLOADS["poisson3d_q7_64c_mixed"]
+    res, xs = {}, {}
+    for prec in (64, 32):
+        p = dgmg.Problem(w["dim"], w["k"], w["L"], precision=prec)
+        p.autotune(nrhs=1)
+        b = torch.from_numpy(inputs.uniform(w["seed"], p.ndofs())).cuda()
+        t, it, rel, x = _time_solves(p, b, reps)
+        res[f"fp{prec}_ms"] = t * 1e3
+        res[f"fp{prec}_iterations"] = int(it[0])
+        xs[prec] = x.clone()
+        p.close()
+        del b, x
+    res["mixed_speedup"] = res["fp64_ms"] / res["fp32_ms"]
+    res["mixed_vs_fp64_rel_diff"] = float(torch.linalg.norm(xs[32] - xs[64]) / torch.linalg.norm(xs[64]))
+    res["ndofs"] = int(xs[64].numel())
+    del xs
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_batched(reps=3):
+    """3-D Q4 32^3, 16 right-hand sides N(0,1) seed 4 solved together (FP32
+    V-cycle in FP64 CG, one launch per kernel for all 16, captured V-cycle,
+    autotuned shapes) vs 16 separate all-FP64 solves."""
+    import torch
+    from paper_2405_18982_amd import dgmg, inputs
+    w = inputs.WORKLOADS["poisson3d_q4_32c_16rhs"]
+    pm = dgmg.Problem(w["dim"], w["k"], w["L"], precision=32, nrhs_max=w["nrhs"])
+    tuned = pm.autotune(nrhs=w["nrhs"])
+    B = torch.from_numpy(inputs.normal(w["seed"], (w["nrhs"], pm.ndofs()))).cuda()
+    tb, itb, _, xb = _time_solves(pm, B, reps)
+    p64 = dgmg.Problem(w["dim"], w["k"], w["L"], precision=64)
+    p64.autotune(nrhs=1)
+    ts, its = 0.0, []
+    x1 = torch.empty_like(B)
+    for j in range(w["nrhs"]):
+        t, it, _, x = _time_solves(p64, B[j].contiguous(), 1, warm=1 if j == 0 else 0)
+        ts += t
+        its.append(int(it[0]))
+        x1[j] = x
+    out = {"ndofs_per_rhs": pm.ndofs(), "nrhs": w["nrhs"], "batched_mixed_ms": tb * 1e3,
+           "batched_iterations": [int(i) for i in itb], "single_fp64_total_ms": ts * 1e3,
+           "single_iterations": its, "speedup": ts / tb,
+           "rel_diff_vs_fp64": float(torch.linalg.norm(xb - x1) / torch.linalg.norm(x1)),
+           "tuned": tuned.strip().splitlines()}
+    pm.close()
+    p64.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +180,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 3-D Q7 mixed and the batched 16-RHS time-to-solution runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU slab decomposition is "
@@ -102,6 +197,7 @@ def main():
     sigma = inputs.sigma_of(k)
     N = 2 ** (L + 1)
     prob = dgmg.Problem(dim, k, L, sigma=sigma)
+    tuned = prob.autotune(nrhs=1)
     ndof = prob.ndofs()
     b = prob.mass(torch.from_numpy(inputs.sine_load(prob.node_coords())).cuda())
     x = torch.empty_like(b)
@@ -134,6 +230,12 @@ def main():
         e1.synchronize()
         return e0.elapsed_time(e1) * 1e-3 / reps
 
+    # calibration copy of a known size: the HBM counters of this plain copy
+    # kernel scale the smoother's counters to bytes (see traffic_from_profile)
+    cal_src = torch.ones(CAL_BYTES // 8, dtype=torch.float64, device="cuda")
+    cal_dst = torch.empty_like(cal_src)
+    cal_dst.copy_(cal_src)
+    torch.cuda.synchronize()
     xin = torch.from_numpy(inputs.uniform(w["seed"], ndof)).cuda()
     yout = torch.empty_like(xin)
     t_apply = timed(lambda: prob.apply(xin, out=yout), 50)
@@ -146,7 +248,7 @@ def main():
     roof = {
         "kernel": "k_smooth (FP64, exact residual) on the finest level, 8 colour launches per step",
         "bound": rf["bound"], "achieved": round(rf["achieved"], 2), "peak": rf["peak"],
-        "unit": rf["unit"], "frac": round(rf["frac"], 4), "traffic": None,
+        "unit": rf["unit"], "frac": round(rf["frac"], 4), "traffic": traffic_from_profile(),
         "algorithmic_bytes_per_launch": sc["bytes"] / nc,
         "algorithmic_flops_per_launch": sc["flops"] / nc,
         "avg_launch_us": t_smooth / nc * 1e6,
@@ -160,6 +262,7 @@ def main():
                            "unit": ra["unit"], "frac": round(ra["frac"], 4)},
         "smooth_gdofs": ndof / t_smooth / 1e9,
         "smooth_step_us": t_smooth * 1e6,
+        "tuned": tuned.strip().splitlines(),
         "pcg_iterations": iters,
         "final_relres": float(rel[0]),
         "fp64_ms_per_solve": ms,
@@ -167,6 +270,7 @@ def main():
 
     if not args.no_mixed:
         pm = dgmg.Problem(dim, k, L, sigma=sigma, precision=dgmg.FP32)
+        pm.autotune(nrhs=1)
         xm = torch.empty_like(b)
         for _ in range(args.warmup):
             pm.solve(b, rtol=rtol, maxit=100, out=xm)
@@ -199,6 +303,9 @@ def main():
         "roofline": roof,
         "components": components,
     }
+    if not args.no_extra:
+        components["q7_64c_fp64_vs_mixed"] = bench_q7_mixed()
+        components["q4_32c_16rhs_batched"] = bench_batched()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dim, k, L, sigma, iters)
     prob.close()

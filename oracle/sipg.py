@@ -288,3 +288,42 @@ class KronApply:
                 T = self._along(self.L if i == dirn else self.M, T, d - 1 - i)
             Y += T
         return self.to_cellwise(Y.reshape(-1))
+
+
+def apply_cells(d, k, N, sigma, x, cells, kappa=1.0):
+    """(A x) restricted to the given cells (cell-wise indices), for meshes too
+    large for a full oracle apply.  Each cell's rows of the Kronecker form only
+    involve the cells within one step in every direction, so the product is
+    taken on that 3^d-cell brick with the matching row/column blocks of the
+    1-D matrices.  Returns an array (len(cells), (k+1)^d) in local
+    lexicographic order."""
+    M, L = sipg_1d(k, N, sigma)
+    L = kappa * L
+    n = k + 1
+    nl = n ** d
+    out = np.zeros((len(cells), nl))
+    for j, c in enumerate(cells):
+        ci = [(int(c) // N ** i) % N for i in range(d)]
+        lo = [max(ci[i] - 1, 0) for i in range(d)]
+        hi = [min(ci[i] + 1, N - 1) for i in range(d)]
+        rows = [np.arange(ci[i] * n, (ci[i] + 1) * n) for i in range(d)]
+        cols = [np.arange(lo[i] * n, (hi[i] + 1) * n) for i in range(d)]
+        # gather the brick, axes ordered (slowest ... fastest) = (d-1 ... 0)
+        shape = tuple((hi[i] - lo[i] + 1) * n for i in reversed(range(d)))
+        X = np.zeros(shape)
+        for cc in itertools.product(*[range(lo[i], hi[i] + 1) for i in reversed(range(d))]):
+            cv = cc[::-1]  # cv[i] = cell coordinate in direction i
+            cell = sum(cv[i] * N ** i for i in range(d))
+            blk = x[cell * nl:(cell + 1) * nl].reshape((n,) * d)
+            sl = tuple(slice((cv[i] - lo[i]) * n, (cv[i] - lo[i] + 1) * n) for i in reversed(range(d)))
+            X[sl] = blk
+        y = np.zeros((n,) * d)
+        for dirn in range(d):
+            T = X
+            for i in range(d):
+                F = (L if i == dirn else M)[np.ix_(rows[i], cols[i])]
+                ax = d - 1 - i
+                T = np.moveaxis(np.tensordot(F, T, axes=([1], [ax])), 0, ax)
+            y += T
+        out[j] = y.reshape(-1)
+    return out

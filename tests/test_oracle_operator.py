@@ -150,3 +150,13 @@ def test_vectorised_patch_indices_equal_loop_definition(d, k, N):
         assert np.array_equal(ps.tiles[j], patch_dofs(d, k, N, v))
         assert np.array_equal(ps.masks[j], kept_mask(d, k, N, v))
         assert ps.colours[j] == colour(v)
+
+
+@pytest.mark.parametrize("d,k,N", [(2, 3, 6), (3, 2, 4), (3, 4, 3)])
+def test_sampled_cell_apply_equals_full_apply(d, k, N):
+    from oracle.sipg import apply_cells
+    x = np.random.default_rng(8).uniform(-1, 1, N ** d * (k + 1) ** d)
+    y = KronApply(d, k, N, sig(k), kappa=1.7)(x).reshape(N ** d, -1)
+    cells = np.arange(N ** d)
+    got = apply_cells(d, k, N, sig(k), x, cells, kappa=1.7)
+    assert np.abs(got - y).max() <= 1e-13 * np.abs(y).max()
