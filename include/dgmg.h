@@ -179,15 +179,18 @@ dgmg_status dgmg_dot(dgmg_ctx* ctx, int level, const double* a, const double* b,
  * eigenvectors satisfy S^T M S = I on the kept nodes. */
 dgmg_status dgmg_patch_eigen(int degree, double sigma, int type, double* S, double* lam);
 
-/* Autotuner: for the finest level and nrhs right-hand sides, time every
- * workgroup shape (patches per workgroup) and patch numbering (plain or
- * XCD-aware) of apply_sipg and smooth_patch, in FP64 and, for a mixed-
- * precision context, FP32, and use the fastest from then on.  Timings run on
- * the CG workspace (its contents are overwritten; FP32 level vectors are
- * allocated if missing).  cache_path (may be NULL) names a JSON file of
- * earlier results keyed by architecture, dim, degree, levels, nrhs, precision
- * and kernel; cached entries are used without timing and new ones appended.
- * report (may be NULL): host buffer receiving one line per decision. */
+/* Autotuner: for nrhs right-hand sides, time every workgroup shape (patches
+ * per workgroup) and patch numbering (plain or XCD-aware) of the FP64
+ * apply_sipg on the finest level, and of smooth_patch on every level 1..L in
+ * the V-cycle's precision, where the shapes also choose whether a patch
+ * fetches its b lines up front (fewer round trips, for latency-bound coarse
+ * levels) or when needed (smaller cache footprint, for the finest level); use
+ * the fastest from then on.  Timings run on the CG workspace and the level
+ * vectors (their contents are overwritten).  cache_path (may be NULL) names a
+ * JSON file of earlier results keyed by architecture, dim, degree, levels,
+ * nrhs, precision, kernel and level; cached entries are used without timing
+ * and new ones added.  report (may be NULL): host buffer receiving one line
+ * per decision.  Drops captured V-cycle graphs. */
 dgmg_status dgmg_autotune(dgmg_ctx* ctx, int nrhs, const char* cache_path, char* report,
                           int report_len);
 

@@ -143,7 +143,8 @@ struct dgmg_ctx {
     int remap = 1;
     double us = 0;
   };
-  Tuning tune_apply[2], tune_smooth[2];
+  Tuning tune_apply[2];
+  Tuning tune_smooth[2][21];  // per precision and level
   hipStream_t cap_stream = nullptr;
   std::vector<hipGraphExec_t> vc_graph;  // index nrhs - 1
   std::string err;
@@ -262,7 +263,7 @@ dgmg_status op_smooth(dgmg_ctx* c, int l, T* x, const T* b, int reverse, int nrh
     const int col = reverse ? nc - 1 - i : i;
     PatchGrid g = grid_colour(c, c->lv[l].N, col);
     if (g.npatch == 0) continue;
-    const auto& tu = c->tune_smooth[prec_index<T>()];
+    const auto& tu = c->tune_smooth[prec_index<T>()][l];
     g.xcd_remap = xcd_remap_flag(tu.remap);
     HIPCHK(c, kset<T>(c).smooth[tu.shape](tab_of<T>(c), g, (T)sc, (T)(1.0 / sc), c->variant, x, b,
                                           nrhs, c->lv[l].ndof, c->stream));
@@ -774,17 +775,16 @@ void write_cache(const char* path, const std::vector<CacheEntry>& es) {
 }
 
 template <typename T>
-dgmg_status tune_kernel(dgmg_ctx* c, int nrhs, bool smooth, T* x, T* y, double* best_us,
-                        dgmg_ctx::Tuning& out) {
-  auto& slot = smooth ? c->tune_smooth[prec_index<T>()] : c->tune_apply[prec_index<T>()];
-  const int L = c->L;
+dgmg_status tune_kernel(dgmg_ctx* c, int nrhs, bool smooth, int level, T* x, T* y,
+                        dgmg_ctx::Tuning& slot) {
+  const int nshapes = smooth ? dgmg::kSmoothShapes : dgmg::kApplyShapes;
   const int reps = smooth ? 3 : 20;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   double best = 1e300;
   dgmg_ctx::Tuning pick = slot;
-  for (int shape = 0; shape < dgmg::kNumShapes; ++shape)
+  for (int shape = 0; shape < nshapes; ++shape)
     for (int remap = 0; remap < 2; ++remap) {
       slot.shape = shape;
       slot.remap = remap;
@@ -792,8 +792,8 @@ dgmg_status tune_kernel(dgmg_ctx* c, int nrhs, bool smooth, T* x, T* y, double* 
       for (int trial = 0; trial < 4; ++trial) {  // trial 0 warms up
         HIPCHK(c, hipEventRecord(e0, c->stream));
         for (int r = 0; r < reps; ++r) {
-          if (smooth) RET(op_smooth<T>(c, L, x, y, 0, nrhs));
-          else RET(op_apply<T>(c, L, x, y, nrhs));
+          if (smooth) RET(op_smooth<T>(c, level, x, y, 0, nrhs));
+          else RET(op_apply<T>(c, level, x, y, nrhs));
         }
         HIPCHK(c, hipEventRecord(e1, c->stream));
         HIPCHK(c, hipEventSynchronize(e1));
@@ -812,8 +812,6 @@ dgmg_status tune_kernel(dgmg_ctx* c, int nrhs, bool smooth, T* x, T* y, double* 
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   slot = pick;
-  out = pick;
-  *best_us = best;
   return DGMG_OK;
 }
 
@@ -825,45 +823,54 @@ DGMG_API dgmg_status dgmg_autotune(dgmg_ctx* c, int nrhs, const char* cache_path
   std::vector<CacheEntry> cache = read_cache(cache_path);
   std::string rep;
   bool dirty = false;
-  const int precs[2] = {64, 32};
-  for (int pi = 0; pi < 2; ++pi) {
-    if (precs[pi] == 32 && c->prec != 32) continue;
-    for (int kk = 0; kk < 2; ++kk) {
-      const bool smooth = kk == 1;
-      const std::string key = tune_key(c, nrhs, precs[pi], smooth ? "smooth" : "apply");
-      dgmg_ctx::Tuning tu;
-      bool found = false;
-      for (const CacheEntry& e : cache)
-        if (e.key == key && e.shape >= 0 && e.shape < dgmg::kNumShapes && (e.remap == 0 || e.remap == 1)) {
-          tu.shape = e.shape;
-          tu.remap = e.remap;
-          tu.us = e.us;
-          found = true;
-        }
-      if (!found) {
-        double us = 0;
-        const long long n = c->lv[c->L].ndof * nrhs;
-        if (pi == 0) {
-          RET(zero_vec<double>(c, c->p, n));
-          RET(zero_vec<double>(c, c->r, n));
-          RET(tune_kernel<double>(c, nrhs, smooth, c->p, smooth ? c->r : c->q, &us, tu));
-        } else {
-          RET(ensure_levels<float>(c, c->L));
-          Level& T = c->lv[c->L];
-          RET(zero_vec<float>(c, T.x32, n));
-          RET(zero_vec<float>(c, T.b32, n));
-          RET(tune_kernel<float>(c, nrhs, smooth, T.x32, T.b32, &us, tu));
-        }
-        cache.push_back({key, tu.shape, tu.remap, tu.us});
-        dirty = true;
+  // decisions: the CG's FP64 apply on the finest level, and the smoother of
+  // the V-cycle's precision on every level it runs on
+  struct Job {
+    int prec;
+    bool smooth;
+    int level;
+  };
+  std::vector<Job> jobs{{64, false, c->L}};
+  for (int l = 1; l <= c->L; ++l) jobs.push_back({c->prec, true, l});
+  if (c->prec == 64) RET(ensure_levels<double>(c, c->L - 1));
+  else RET(ensure_levels<float>(c, c->L));
+  for (const Job& jb : jobs) {
+    char kname[32];
+    if (jb.smooth) std::snprintf(kname, sizeof(kname), "smooth/l%d", jb.level);
+    else std::snprintf(kname, sizeof(kname), "apply");
+    const std::string key = tune_key(c, nrhs, jb.prec, kname);
+    const int pi = jb.prec == 64 ? 0 : 1;
+    dgmg_ctx::Tuning& slot = jb.smooth ? c->tune_smooth[pi][jb.level] : c->tune_apply[pi];
+    const int nshapes = jb.smooth ? dgmg::kSmoothShapes : dgmg::kApplyShapes;
+    bool found = false;
+    for (const CacheEntry& e : cache)
+      if (e.key == key && e.shape >= 0 && e.shape < nshapes && (e.remap == 0 || e.remap == 1)) {
+        slot.shape = e.shape;
+        slot.remap = e.remap;
+        slot.us = e.us;
+        found = true;
       }
-      auto& slot = smooth ? c->tune_smooth[pi] : c->tune_apply[pi];
-      slot = tu;
-      char line[256];
-      std::snprintf(line, sizeof(line), "%s shape=%d remap=%d us=%.3f%s\n", key.c_str(), tu.shape,
-                    tu.remap, tu.us, found ? " (cached)" : "");
-      rep += line;
+    if (!found) {
+      Level& Lv = c->lv[jb.level];
+      const long long n = Lv.ndof * nrhs;
+      if (jb.prec == 64) {
+        double* x = jb.level == c->L ? c->p : Lv.x64;
+        double* y = jb.level == c->L ? (jb.smooth ? c->r : c->q) : Lv.b64;
+        RET(zero_vec<double>(c, x, n));
+        RET(zero_vec<double>(c, y, n));
+        RET(tune_kernel<double>(c, nrhs, jb.smooth, jb.level, x, y, slot));
+      } else {
+        RET(zero_vec<float>(c, Lv.x32, n));
+        RET(zero_vec<float>(c, Lv.b32, n));
+        RET(tune_kernel<float>(c, nrhs, jb.smooth, jb.level, Lv.x32, Lv.b32, slot));
+      }
+      cache.push_back({key, slot.shape, slot.remap, slot.us});
+      dirty = true;
     }
+    char line[256];
+    std::snprintf(line, sizeof(line), "%s shape=%d remap=%d us=%.3f%s\n", key.c_str(), slot.shape,
+                  slot.remap, slot.us, found ? " (cached)" : "");
+    rep += line;
   }
   if (dirty) write_cache(cache_path, cache);
   drop_graphs(c);  // graphs hold the previous launch shapes

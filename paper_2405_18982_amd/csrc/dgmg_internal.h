@@ -8,7 +8,8 @@
 namespace dgmg {
 
 constexpr int kMaxDegree = 7;
-constexpr int kNumShapes = 2;  // workgroup shapes of the tuned kernels
+constexpr int kApplyShapes = 2;   // workgroup shapes of apply
+constexpr int kSmoothShapes = 4;  // workgroup shapes x prefetch of b for smooth
 
 // Reference (h = 1, kappa = 1) 1-D tables of Q_K on a two-cell patch, in the
 // arithmetic type T of the kernels that read them.  Built on the host in FP64
@@ -48,12 +49,13 @@ struct PatchGrid {
 // [nrhs][ndof] device arrays; `tab` points to a device Tab<K, T>.
 template <typename T>
 struct KernelSet {
-  // apply and smooth come in kNumShapes workgroup shapes (patches per workgroup)
-  hipError_t (*apply[2])(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
+  // apply and smooth come in several tuned shapes (patches per workgroup; for
+  // the smoother also whether b is prefetched)
+  hipError_t (*apply[kApplyShapes])(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
                          long long ndof, hipStream_t s);
   hipError_t (*mass)(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
                      long long ndof, hipStream_t s);
-  hipError_t (*smooth[2])(const void* tab, PatchGrid g, T scale, T inv_scale, int local_variant,
+  hipError_t (*smooth[kSmoothShapes])(const void* tab, PatchGrid g, T scale, T inv_scale, int local_variant,
                           T* x, const T* b, int nrhs, long long ndof, hipStream_t s);
   hipError_t (*restrict_residual)(const void* tab, PatchGrid g, T scale, const T* x, const T* b,
                                   T* bc, int nrhs, long long ndof, long long ndof_c,

@@ -30,15 +30,18 @@ def rel(a, b):
 
 
 def force_cache(path, dim, k, L, nrhs, shape, remap):
+    """Cache entries forcing the FP64 apply (shape mod 2) and the FP64
+    smoother on every level (shape 0..3) to one choice."""
     lines = []
-    for kern in ("apply", "smooth"):
+    keys = [("apply", shape % 2)] + [(f"smooth/l{l}", shape) for l in range(1, L + 1)]
+    for kern, sh in keys:
         key = f"gfx950/d{dim}/k{k}/L{L}/nrhs{nrhs}/fp64/{kern}"
-        lines.append(f'  "{key}": {{"shape": {shape}, "remap": {remap}, "us": 1.000}}')
+        lines.append(f'  "{key}": {{"shape": {sh}, "remap": {remap}, "us": 1.000}}')
     path.write_text("{\n" + ",\n".join(lines) + "\n}\n")
 
 
 @pytest.mark.parametrize("dim,k,L", [(2, 2, 3), (2, 5, 2), (3, 1, 2), (3, 2, 2), (3, 3, 2), (3, 4, 1)])
-@pytest.mark.parametrize("shape,remap", list(itertools.product([0, 1], [0, 1])))
+@pytest.mark.parametrize("shape,remap", list(itertools.product([0, 1, 2, 3], [0, 1])))
 def test_every_tunable_shape_matches_oracle(tmp_path, dim, k, L, shape, remap):
     note(f"tuned shape={shape} remap={remap} d={dim} k={k} L={L}")
     nrhs = 2
@@ -46,7 +49,7 @@ def test_every_tunable_shape_matches_oracle(tmp_path, dim, k, L, shape, remap):
     cache = tmp_path / "tune.json"
     force_cache(cache, dim, k, L, nrhs, shape, remap)
     rep = prob.autotune(nrhs=nrhs, cache=str(cache))
-    assert rep.count("(cached)") == 2 and f"shape={shape} remap={remap}" in rep
+    assert rep.count("(cached)") == 1 + L and f"shape={shape} remap={remap}" in rep
     N = 2 ** (L + 1)
     sig = inputs.sigma_of(k)
     X = inputs.uniform(41, (nrhs, prob.ndofs()))
@@ -68,6 +71,7 @@ def test_tuning_writes_and_reads_cache(tmp_path):
     prob = dgmg.Problem(3, 3, 3, precision=32, nrhs_max=4)
     cache = tmp_path / "tune.json"
     rep1 = prob.autotune(nrhs=4, cache=str(cache))
+    # FP64 apply on the finest level + FP32 smoother on levels 1..3
     assert len(rep1.strip().splitlines()) == 4 and "(cached)" not in rep1
     txt = cache.read_text()
     assert txt.startswith("{") and txt.count('"shape"') == 4
