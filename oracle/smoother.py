@@ -6,11 +6,19 @@ inverse3d, fast_inverse).
 For every colour in the given order, and every patch j of that colour:
     r_j = local residual on V_j
     x|V_j += A[V_j, V_j]^{-1} r_j
-Two readings of the local residual:
-  'exact'  r_j = (b - A x)|V_j, the residual of eq. (residual) restricted to V_j;
-  'local'  r_j = b|V_j - A[V_j, Vbar_j] x|Vbar_j, the paper-literal Dirichlet
-           kernel that only sees the patch cells (inconsistent by design).
-Both use the global matrix entries restricted to the index sets.
+Local spaces and residuals:
+  'exact'  Dirichlet kernel: V_j drops the patch-boundary nodes on interior
+           faces; r_j = (b - A x)|V_j, the residual of eq. (residual)
+           restricted to V_j;
+  'local'  the paper-literal Dirichlet kernel: r_j = b|V_j - A[V_j, Vbar_j]
+           x|Vbar_j with Vbar_j the patch cells only (inconsistent by design);
+  'full'   the Full kernel (Sec. 3.1): V_j = every node of the patch cells;
+           its domain of dependence reaches into the face-neighbour cells,
+           which belong to other patches of the same colour, so the residual
+           is updated globally: r = b - A x once per colour, and every patch
+           of the colour corrects from that r (additive inside a colour,
+           multiplicative across colours).
+All use the global matrix entries restricted to the index sets.
 
 `smooth_dense` is the definition itself: patches visited one after another,
 residual rows taken from the assembled sparse matrix, dense local solves.
@@ -34,6 +42,12 @@ def smooth_dense(A, x, b, ps, order, mode="exact"):
     x = np.array(x, dtype=np.float64, copy=True)
     A = A.tocsr()
     for c in order:
+        if mode == "full":
+            r = b - A @ x
+            for j in ps.of_colour(c):
+                V = ps.vbar(j)
+                x[V] += np.linalg.solve(A[V][:, V].toarray(), r[V])
+            continue
         for j in ps.of_colour(c):
             V = ps.vj(j)
             if mode == "exact":
@@ -50,7 +64,9 @@ def smooth_dense(A, x, b, ps, order, mode="exact"):
 
 class PatchFD:
     """1-D patch matrices and their generalised eigenpairs for every patch
-    type along one direction (interior, touching x=0, touching x=1, both)."""
+    type along one direction (interior, touching x=0, touching x=1, both):
+    S, lam on the Dirichlet local space, Sf, lamf on the whole patch (Full
+    kernel)."""
 
     def __init__(self, k, N, sigma, kappa=1.0):
         M, L = sipg_1d(k, N, sigma)
@@ -58,7 +74,7 @@ class PatchFD:
         n = k + 1
         self.k, self.N = k, N
         self.S, self.lam, self.Mt, self.Lt, self.keep = {}, {}, {}, {}, {}
-        self.Mpatch, self.Lpatch = {}, {}
+        self.Mpatch, self.Lpatch, self.Sf, self.lamf = {}, {}, {}, {}
         for vi in range(1, N):
             t = patch_type_1d(N, vi)
             if t in self.S:
@@ -71,6 +87,7 @@ class PatchFD:
             self.S[t], self.lam[t] = S, lam
             self.Mt[t], self.Lt[t], self.keep[t] = Mt, Lt, keep
             self.Mpatch[t], self.Lpatch[t] = Mp, Lp
+            self.lamf[t], self.Sf[t] = sla.eigh(Lp, Mp)
 
 
 def _along(A1, T, axis):
@@ -81,22 +98,24 @@ def _along(A1, T, axis):
     return np.moveaxis(Y, -1, axis)
 
 
-def fd_inverse(fd, types, R):
+def fd_inverse(fd, types, R, full=False):
     """Apply A_j^{-1} by fast diagonalisation to a batch of kept-set tiles R
     (shape (np, n_{d-1}, ..., n_0)) of patches sharing the type tuple `types`
-    (types[i] = type along direction i)."""
+    (types[i] = type along direction i); `full` selects the whole-patch
+    eigenpairs of the Full kernel."""
+    S, lm = (fd.Sf, fd.lamf) if full else (fd.S, fd.lam)
     d = len(types)
     T = R
     for i in range(d):
-        T = _along(fd.S[types[i]].T, T, d - i)
+        T = _along(S[types[i]].T, T, d - i)
     lam = np.zeros(T.shape[1:])
     for i in range(d):
         shape = [1] * d
         shape[d - 1 - i] = -1
-        lam = lam + fd.lam[types[i]].reshape(shape)
+        lam = lam + lm[types[i]].reshape(shape)
     T = T / lam[None]
     for i in range(d):
-        T = _along(fd.S[types[i]], T, d - i)
+        T = _along(S[types[i]], T, d - i)
     return T
 
 
@@ -116,13 +135,15 @@ class FDSmoother:
         self.groups = {key: np.array(val) for key, val in self.groups.items()}
 
     def _kept_slices(self, types):
+        if self.mode == "full":
+            return tuple(np.arange(2 * (self.k + 1)) for _ in range(self.d))
         return tuple(np.array(self.fd.keep[types[i]]) for i in reversed(range(self.d)))
 
     def step(self, x, b, order):
         d = self.d
         x = np.array(x, dtype=np.float64, copy=True)
         for c in order:
-            r = b - self.apply(x) if self.mode == "exact" else None
+            r = b - self.apply(x) if self.mode in ("exact", "full") else None
             updates = []
             for (cc, types), js in self.groups.items():
                 if cc != c:
@@ -130,7 +151,7 @@ class FDSmoother:
                 tiles = self.ps.tiles[js]  # (np, E,...,E)
                 ks = self._kept_slices(types)
                 sub = tiles[(slice(None),) + np.ix_(*ks)]
-                if self.mode == "exact":
+                if self.mode in ("exact", "full"):
                     R = r[sub]
                 else:
                     X = x[tiles]
@@ -142,7 +163,7 @@ class FDSmoother:
                             T = _along(mat, T, d - i)
                         AX += T
                     R = b[sub] - AX[(slice(None),) + np.ix_(*ks)]
-                updates.append((sub, fd_inverse(self.fd, types, R)))
+                updates.append((sub, fd_inverse(self.fd, types, R, self.mode == "full")))
             for sub, dx in updates:
                 x[sub] += dx
         return x
