@@ -14,6 +14,14 @@ are kept so that they are smoothed at all.  V_j is the tensor product of the
 per-direction kept sets; the domain of dependence of the paper-literal kernel
 is all DoFs of the patch cells.
 
+Clamped local space (Sec. 3.1, Fig. hermite_type): the patch functions with
+v = 0 and dv/dn = 0 on the patch boundary.  Along one direction these are
+the vectors of the two-cell patch whose value and derivative vanish at each
+end that lies on an interior mesh face (2k - 2 of them for an interior
+patch); at an end on the domain boundary nothing is clamped, for the same
+reason the Dirichlet space keeps those nodes.  The d-D space is the tensor
+product of the 1-D ones.
+
 Colours: colour(v) = sum_i ((v_i - 1) mod 2) 2^i, i.e. 2^d colours; patches of
 one colour share no cell, and colour 0 (all v_i odd) tiles the mesh by the
 children of the coarse cells.
@@ -43,6 +51,40 @@ def kept_1d(k, N, vi):
     if vi == N - 1:
         keep = keep + [2 * k + 1]
     return keep
+
+
+def clamped_basis_1d(k, ptype):
+    """Orthonormal basis (columns, shape (2k+2, m)) of the 1-D clamped space
+    of a patch type: the null space of the end constraints v(end) = 0 and
+    v'(end) = 0 at every end not on the domain boundary (type bit 0: the left
+    end lies on x = 0, bit 1: the right end on x = 1).  Node values at the
+    ends are the traces (Gauss-Lobatto end points); the derivative at the
+    left end is phi'(0) . v on the left cell, at the right end phi'(1) . v on
+    the right cell (reference cell; h only scales the constraint)."""
+    import scipy.linalg as sla
+
+    from .basis import Basis1D
+    n = k + 1
+    E = 2 * n
+    bs = Basis1D(k)
+    rows = []
+    if not ptype & 1:
+        r = np.zeros(E)
+        r[0] = 1.0
+        rows.append(r)
+        r = np.zeros(E)
+        r[:n] = bs.d0
+        rows.append(r)
+    if not ptype & 2:
+        r = np.zeros(E)
+        r[E - 1] = 1.0
+        rows.append(r)
+        r = np.zeros(E)
+        r[n:] = bs.d1
+        rows.append(r)
+    if not rows:
+        return np.eye(E)
+    return sla.null_space(np.array(rows))
 
 
 def patch_type_1d(N, vi):

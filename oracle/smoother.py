@@ -18,6 +18,13 @@ Local spaces and residuals:
            is updated globally: r = b - A x once per colour, and every patch
            of the colour corrects from that r (additive inside a colour,
            multiplicative across colours).
+  'clamped' the clamped kernel (Sec. 3.1): V_j = patch functions with zero
+           value and normal derivative on the patch boundary (a subspace of
+           the patch space, basis C = tensor product of the 1-D bases of
+           `clamped_basis_1d`); r_j = C^T (b - A x)|patch and the correction
+           C (C^T A_patch C)^{-1} r_j.  The face terms that couple the patch
+           to outside cells act on rows that C^T annihilates, so r_j only
+           depends on the patch cells and same-colour patches are independent.
 All use the global matrix entries restricted to the index sets.
 
 `smooth_dense` is the definition itself: patches visited one after another,
@@ -33,7 +40,7 @@ import itertools
 import numpy as np
 import scipy.linalg as sla
 
-from .patches import PatchSet, kept_1d, patch_type_1d
+from .patches import PatchSet, clamped_basis_1d, kept_1d, patch_type_1d
 from .sipg import KronApply, sipg_1d
 
 
@@ -47,6 +54,15 @@ def smooth_dense(A, x, b, ps, order, mode="exact"):
             for j in ps.of_colour(c):
                 V = ps.vbar(j)
                 x[V] += np.linalg.solve(A[V][:, V].toarray(), r[V])
+            continue
+        if mode == "clamped":
+            for j in ps.of_colour(c):
+                V = ps.vbar(j)  # tile order: [p_{d-1}, ..., p_0], p_0 fastest
+                C = np.ones((1, 1))
+                for i in reversed(range(ps.d)):
+                    C = np.kron(C, clamped_basis_1d(ps.k, patch_type_1d(ps.N, ps.verts[j][i])))
+                r = C.T @ (b[V] - A[V] @ x)
+                x[V] += C @ np.linalg.solve(C.T @ A[V][:, V].toarray() @ C, r)
             continue
         for j in ps.of_colour(c):
             V = ps.vj(j)
@@ -66,7 +82,7 @@ class PatchFD:
     """1-D patch matrices and their generalised eigenpairs for every patch
     type along one direction (interior, touching x=0, touching x=1, both):
     S, lam on the Dirichlet local space, Sf, lamf on the whole patch (Full
-    kernel)."""
+    kernel), Sc = C S_C, lamc on the clamped space with basis C."""
 
     def __init__(self, k, N, sigma, kappa=1.0):
         M, L = sipg_1d(k, N, sigma)
@@ -75,6 +91,7 @@ class PatchFD:
         self.k, self.N = k, N
         self.S, self.lam, self.Mt, self.Lt, self.keep = {}, {}, {}, {}, {}
         self.Mpatch, self.Lpatch, self.Sf, self.lamf = {}, {}, {}, {}
+        self.Sc, self.lamc = {}, {}
         for vi in range(1, N):
             t = patch_type_1d(N, vi)
             if t in self.S:
@@ -88,6 +105,10 @@ class PatchFD:
             self.Mt[t], self.Lt[t], self.keep[t] = Mt, Lt, keep
             self.Mpatch[t], self.Lpatch[t] = Mp, Lp
             self.lamf[t], self.Sf[t] = sla.eigh(Lp, Mp)
+            C = clamped_basis_1d(k, t)
+            if C.shape[1] > 0:
+                lc, Sc = sla.eigh(C.T @ Lp @ C, C.T @ Mp @ C)
+                self.lamc[t], self.Sc[t] = lc, C @ Sc
 
 
 def _along(A1, T, axis):
@@ -98,12 +119,14 @@ def _along(A1, T, axis):
     return np.moveaxis(Y, -1, axis)
 
 
-def fd_inverse(fd, types, R, full=False):
-    """Apply A_j^{-1} by fast diagonalisation to a batch of kept-set tiles R
-    (shape (np, n_{d-1}, ..., n_0)) of patches sharing the type tuple `types`
-    (types[i] = type along direction i); `full` selects the whole-patch
-    eigenpairs of the Full kernel."""
-    S, lm = (fd.Sf, fd.lamf) if full else (fd.S, fd.lam)
+def fd_inverse(fd, types, R, space="dirichlet"):
+    """Apply A_j^{-1} by fast diagonalisation to a batch of tiles R (shape
+    (np, n_{d-1}, ..., n_0)) of patches sharing the type tuple `types`
+    (types[i] = type along direction i).  space 'dirichlet': R holds the kept
+    set; 'full': the whole tile; 'clamped': the whole tile, and S = C S_C maps
+    between tile values and the eigenbasis of the clamped space."""
+    S, lm = {"dirichlet": (fd.S, fd.lam), "full": (fd.Sf, fd.lamf),
+             "clamped": (fd.Sc, fd.lamc)}[space]
     d = len(types)
     T = R
     for i in range(d):
@@ -123,6 +146,10 @@ class FDSmoother:
     """Vectorised smoothing step for one level (cell-wise layout)."""
 
     def __init__(self, d, k, N, sigma, kappa=1.0, mode="exact", apply=None):
+        if mode == "clamped" and k < 3:
+            # per direction a cell lies in two patches whose clamped spaces
+            # together span 2(k - 1) of the k + 1 cell polynomials
+            raise ValueError("the clamped spaces cover Q_k only for k >= 3")
         self.d, self.k, self.N, self.mode = d, k, N, mode
         self.ps = PatchSet(d, k, N)
         self.fd = PatchFD(k, N, sigma, kappa)
@@ -135,7 +162,7 @@ class FDSmoother:
         self.groups = {key: np.array(val) for key, val in self.groups.items()}
 
     def _kept_slices(self, types):
-        if self.mode == "full":
+        if self.mode in ("full", "clamped"):
             return tuple(np.arange(2 * (self.k + 1)) for _ in range(self.d))
         return tuple(np.array(self.fd.keep[types[i]]) for i in reversed(range(self.d)))
 
@@ -143,7 +170,7 @@ class FDSmoother:
         d = self.d
         x = np.array(x, dtype=np.float64, copy=True)
         for c in order:
-            r = b - self.apply(x) if self.mode in ("exact", "full") else None
+            r = b - self.apply(x) if self.mode in ("exact", "full", "clamped") else None
             updates = []
             for (cc, types), js in self.groups.items():
                 if cc != c:
@@ -151,7 +178,7 @@ class FDSmoother:
                 tiles = self.ps.tiles[js]  # (np, E,...,E)
                 ks = self._kept_slices(types)
                 sub = tiles[(slice(None),) + np.ix_(*ks)]
-                if self.mode in ("exact", "full"):
+                if self.mode in ("exact", "full", "clamped"):
                     R = r[sub]
                 else:
                     X = x[tiles]
@@ -163,7 +190,8 @@ class FDSmoother:
                             T = _along(mat, T, d - i)
                         AX += T
                     R = b[sub] - AX[(slice(None),) + np.ix_(*ks)]
-                updates.append((sub, fd_inverse(self.fd, types, R, self.mode == "full")))
+                space = self.mode if self.mode in ("full", "clamped") else "dirichlet"
+                updates.append((sub, fd_inverse(self.fd, types, R, space)))
             for sub, dx in updates:
                 x[sub] += dx
         return x

@@ -9,7 +9,7 @@ import pytest
 from oracle.adjoint import closed_form_dkappa, dense_adjoint
 from oracle.fdsolve import GlobalFD
 from oracle.multigrid import Hierarchy, fractional_iterations, gmres, pcg
-from oracle.patches import PatchSet
+from oracle.patches import PatchSet, clamped_basis_1d, patch_type_1d
 from oracle.rhs import load_vector, sine_load
 from oracle.sipg import kron_operator
 from oracle.smoother import FDSmoother, colour_orders, smooth_dense
@@ -21,9 +21,12 @@ def sig(k):
     return 2.0 * (k + 1) ** 2
 
 
-@pytest.mark.parametrize("d,k,N", [(2, 1, 4), (2, 2, 4), (2, 3, 5), (3, 1, 4), (3, 2, 3)])
-@pytest.mark.parametrize("mode", ["exact", "local", "full"])
+@pytest.mark.parametrize("d,k,N", [(2, 1, 4), (2, 2, 4), (2, 3, 5), (2, 4, 4), (3, 1, 4), (3, 2, 3),
+                                   (3, 3, 3)])
+@pytest.mark.parametrize("mode", ["exact", "local", "full", "clamped"])
 def test_fd_smoother_equals_sequential_dense_definition(d, k, N, mode):
+    if mode == "clamped" and k < 3:
+        pytest.skip("the clamped kernel needs k >= 3")
     A = kron_operator(d, k, N, sig(k), kappa=1.5)
     ps = PatchSet(d, k, N)
     rng = np.random.default_rng(3)
@@ -89,13 +92,89 @@ def test_full_colour_is_block_jacobi_on_the_colour_partition():
     assert np.linalg.norm(seq - ref) > 1e-6 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("k", [3, 4, 7])
+def test_clamped_space_dimensions_and_constraints(k):
+    """Interior patches have (2k-2)^d unknowns (Sec. 3.3: 4^3 for Q3);
+    every basis vector has zero trace and zero derivative at the clamped ends
+    (checked with derivatives of the Lagrange basis evaluated independently
+    by finite differences of its values)."""
+    from oracle.basis import Basis1D
+    n = k + 1
+    bs = Basis1D(k)
+    dims = {t: clamped_basis_1d(k, t).shape[1] for t in range(4)}
+    assert dims == {0: 2 * k - 2, 1: 2 * k, 2: 2 * k, 3: 2 * k + 2}
+    C = clamped_basis_1d(k, 0)
+    # values at the two patch ends, and one-sided second-order differences of
+    # the represented functions there (left end: left cell at 0; right end:
+    # right cell at 1)
+    h = 1e-5
+    V0 = bs.eval(np.array([0.0, h, 2 * h]))[0] @ C[:n]
+    V1 = bs.eval(np.array([1.0, 1 - h, 1 - 2 * h]))[0] @ C[n:]
+    assert np.abs(V0[0]).max() < 1e-13 and np.abs(V1[0]).max() < 1e-13
+    der0 = (-3 * V0[0] + 4 * V0[1] - V0[2]) / (2 * h)
+    der1 = (3 * V1[0] - 4 * V1[1] + V1[2]) / (2 * h)
+    assert np.abs(der0).max() < 1e-6 and np.abs(der1).max() < 1e-6
+    # the free directions are not constrained: interior-node values vary
+    assert np.linalg.matrix_rank(C[1:2 * n - 1]) == 2 * k - 2
+    assert np.allclose(C.T @ C, np.eye(2 * k - 2), atol=1e-12)
+
+
+def test_clamped_residual_needs_only_the_patch():
+    """C^T (b - A x)|patch equals C^T (b|patch - A[patch, patch] x|patch): the
+    face terms coupling the patch to outside cells vanish on the clamped
+    space, so the local residual is exact from patch data alone."""
+    d, k, N = 3, 3, 4
+    A = kron_operator(d, k, N, sig(k)).tocsr()
+    ps = PatchSet(d, k, N)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal(A.shape[0])
+    b = rng.standard_normal(A.shape[0])
+    for j in range(len(ps.verts)):
+        V = ps.vbar(j)
+        C = np.ones((1, 1))
+        for i in reversed(range(d)):
+            C = np.kron(C, clamped_basis_1d(k, patch_type_1d(N, ps.verts[j][i])))
+        full = C.T @ (b[V] - A[V] @ x)
+        local = C.T @ (b[V] - A[V][:, V] @ x[V])
+        assert np.linalg.norm(full - local) <= 1e-12 * np.linalg.norm(full)
+    # the Dirichlet space does not have this property (its residual needs the
+    # outside traces)
+    j = int(np.nonzero((ps.verts == 2).all(axis=1))[0][0])
+    V, Vj = ps.vbar(j), ps.vj(j)
+    assert np.linalg.norm((A[Vj] @ x) - A[Vj][:, V] @ x[V]) > 1e-3
+
+
+def test_clamped_spaces_span_qk_only_from_k3():
+    """The union of the clamped spaces of the two patches containing a cell
+    (per direction) has dimension min(2(k-1), k+1): short of Q_k for k = 2,
+    which leaves the k = 2 smoother (and V-cycle) singular."""
+    for k, full in ((2, False), (3, True), (4, True), (5, True)):
+        n = k + 1
+        C = clamped_basis_1d(k, 0)
+        # the cell is the right cell of one patch and the left cell of the next
+        span = np.hstack([C[n:], C[:n]])
+        assert (np.linalg.matrix_rank(span, tol=1e-10) == n) == full, k
+    with pytest.raises(ValueError):
+        FDSmoother(2, 2, 4, sig(2), mode="clamped")
+
+
+def test_clamped_fixed_point_is_solution():
+    d, k, N = 2, 3, 4
+    A = kron_operator(d, k, N, sig(k))
+    b = np.random.default_rng(13).standard_normal(A.shape[0])
+    u = GlobalFD(d, k, N, sig(k)).solve(b)
+    x = FDSmoother(d, k, N, sig(k), mode="clamped").step(u, b, list(range(4)))
+    assert np.linalg.norm(x - u) <= 1e-12 * np.linalg.norm(u)
+
+
 def _vcycle_matrix(H):
     n = H.ndofs(H.L)
     return np.stack([H.vcycle(e) for e in np.eye(n)], axis=1)
 
 
-@pytest.mark.parametrize("mode", ["exact", "full"])
-@pytest.mark.parametrize("d,k,L", [(2, 1, 2), (2, 2, 2), (3, 1, 1)])
+@pytest.mark.parametrize("d,k,L,mode", [(2, 1, 2, "exact"), (2, 2, 2, "exact"), (3, 1, 1, "exact"),
+                                        (2, 1, 2, "full"), (2, 2, 2, "full"), (3, 1, 1, "full"),
+                                        (2, 3, 2, "clamped"), (2, 4, 1, "clamped")])
 def test_vcycle_symmetric_positive_definite(d, k, L, mode):
     B = _vcycle_matrix(Hierarchy(d, k, L, sig(k), mode=mode))
     assert np.abs(B - B.T).max() <= 1e-13 * np.abs(B).max()
@@ -202,6 +281,24 @@ def test_gmres_nu_weak_pin_table1_full(k):
         nus[mode] = fractional_iterations(gmres(H.apply[2], H.vcycle, b, rtol=1e-8)[2])
     assert nus["full"] < nus["exact"], nus
     assert abs(nus["full"] - ref) <= 1.0, (nus, ref)
+
+
+@pytest.mark.slow
+def test_gmres_nu_weak_pin_table2_clamped():
+    """Clamped kernel (Table 2, right half), L = 2: more iterations than the
+    Dirichlet kernel (smaller subspace), decreasing with the degree as
+    printed, and within a factor 2.5 of the printed values."""
+    nus = {}
+    for k in (3, 4, 5):
+        H = Hierarchy(3, k, 2, 2.0 * k * (k + 1), mode="clamped")
+        b = load_vector(3, k, H.N[2], lambda X: np.ones(X.shape[0]))
+        nus[k] = fractional_iterations(gmres(H.apply[2], H.vcycle, b, rtol=1e-8, maxit=100)[2])
+    ref = {(L, kk): nu for L, kk, nu in _golden_nu("table2_clamped_nu.txt")}
+    dir_ref = {(L, kk): nu for L, kk, nu in _golden_nu()}
+    assert nus[3] > nus[4] > nus[5], nus
+    for k in (3, 4, 5):
+        assert nus[k] > dir_ref[(2, k)]
+        assert ref[(2, k)] / 2.5 <= nus[k] <= 2.5 * ref[(2, k)], (k, nus[k], ref[(2, k)])
 
 
 def test_nu_formula_counts_steps():
