@@ -11,7 +11,8 @@ V-cycle, PCG) with inputs resident in HBM.  `value` is solved DoFs per second
 Also reported: apply and smoothing-step throughput (GDoF/s) measured with HIP
 events on the library's stream, the mixed-precision (FP32 V-cycle) solve on
 the same problem, the roofline position of the dominant kernel (the patch
-smoother on the finest level), time to solution of the 3-D Q7 64^3 problem
+smoother on the finest level), the Full vertex-patch kernel's smoothing step
+and solve on the same problem, time to solution of the 3-D Q7 64^3 problem
 (134M DoFs) all-FP64 vs mixed and of 16 batched right-hand sides (3-D Q4 32^3)
 vs 16 single FP64 solves, and the FP64 CPU oracle timed on a bounded sample of
 the bench workload.  Kernel workgroup shapes are autotuned before timing.
@@ -173,6 +174,32 @@ def bench_batched(reps=3):
     return out
 
 
+def bench_full_kernel(b, xin, t_smooth_dirichlet, ms_dirichlet, reps=5):
+    """The Full vertex-patch kernel (whole patch, residual once per colour) on
+    the bench workload: smoothing-step time against the Dirichlet kernel's
+    (the paper measures the Full step 4-5x slower) and the time to 1e-10."""
+    import torch
+    from paper_2405_18982_amd import dgmg, inputs
+    w = inputs.WORKLOADS[WORKLOAD]
+    pf = dgmg.Problem(w["dim"], w["k"], w["L"], variant=dgmg.SMOOTH_FULL)
+    tuned = pf.autotune(nrhs=1)
+    xs = xin.clone()
+    pf.smooth(xs, b)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        pf.smooth(xs, b)
+    e1.record()
+    e1.synchronize()
+    t_step = e0.elapsed_time(e1) * 1e-3 / 20
+    t, it, rel, _ = _time_solves(pf, b, reps)
+    pf.close()
+    return {"smooth_step_us": t_step * 1e6, "step_vs_dirichlet": t_step / t_smooth_dirichlet,
+            "ms_per_solve": t * 1e3, "pcg_iterations": int(it[0]),
+            "solve_vs_dirichlet": t * 1e3 / ms_dirichlet, "tuned": tuned.strip().splitlines()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +331,7 @@ def main():
         "components": components,
     }
     if not args.no_extra:
+        components["full_kernel"] = bench_full_kernel(b, xin, t_smooth, ms)
         components["q7_64c_fp64_vs_mixed"] = bench_q7_mixed()
         components["q4_32c_16rhs_batched"] = bench_batched()
     if not args.no_cpu_baseline:

@@ -59,13 +59,21 @@ typedef enum {
 
 enum { DGMG_FP64 = 64, DGMG_FP32 = 32 };
 
-/* Local residual of the Dirichlet vertex-patch kernel (Sec. 3.1, Alg. 1):
+/* Local space and residual of the vertex-patch smoother (Sec. 3.1, Alg. 1).
+ * Dirichlet kernel (V_j drops the patch-boundary nodes on interior faces):
  * EXACT uses (b - A x) restricted to V_j, i.e. it adds the coupling of V_j to
  *   the traces of the face-neighbour cells outside the patch; the smoother is
  *   then an exact multiplicative subspace correction and the V-cycle symmetric.
  * LOCAL is the paper-literal kernel: r_j = b|V_j - A[V_j, Vbar_j] x|Vbar_j with
- *   Vbar_j the patch cells only (inconsistent residual; not for CG). */
-enum { DGMG_SMOOTH_EXACT = 0, DGMG_SMOOTH_LOCAL = 1 };
+ *   Vbar_j the patch cells only (inconsistent residual; not for CG).
+ * FULL is the Full kernel: V_j = every node of the patch cells.  Its domain of
+ *   dependence reaches into face-neighbour cells that other patches of the
+ *   same colour update, so the residual is taken once per colour (the global
+ *   update of Sec. 3.1): every patch of a colour corrects from b - A x of the
+ *   colour's entry state (additive inside a colour, multiplicative across
+ *   colours; the V-cycle stays symmetric).  The library keeps a second copy of
+ *   x per level for it. */
+enum { DGMG_SMOOTH_EXACT = 0, DGMG_SMOOTH_LOCAL = 1, DGMG_SMOOTH_FULL = 2 };
 
 /* Create a context for the problem above.  dim in {2,3}; 1 <= degree <= 7;
  * 1 <= finest_level with ndofs(L) < 2^40; penalty_sigma > 0 (the operator is
@@ -77,8 +85,9 @@ dgmg_status dgmg_setup_mesh(int dim, int degree, int finest_level, double penalt
 
 /* Allocate device tables and workspaces.  vcycle_precision: DGMG_FP64, or
  * DGMG_FP32 for the mixed form (V-cycle in FP32 inside FP64 CG, Sec. 5.2).
- * smoother_variant: DGMG_SMOOTH_EXACT or DGMG_SMOOTH_LOCAL.  nrhs_max >= 1
- * bounds the nrhs of every later call.  hip_stream: hipStream_t or NULL. */
+ * smoother_variant: DGMG_SMOOTH_EXACT, DGMG_SMOOTH_LOCAL or DGMG_SMOOTH_FULL.
+ * nrhs_max >= 1 bounds the nrhs of every later call.  hip_stream: hipStream_t
+ * or NULL. */
 dgmg_status dgmg_setup_levels(dgmg_ctx* ctx, int vcycle_precision, int smoother_variant,
                               int nrhs_max, void* hip_stream);
 
@@ -118,9 +127,10 @@ dgmg_status dgmg_apply_mass(dgmg_ctx* ctx, int level, const double* x, double* y
  * descending when reverse_colours != 0), every patch of the colour computes
  * its local residual on V_j and adds A[V_j,V_j]^{-1} r_j, the local inverse by
  * fast diagonalisation (Sec. 3.2, eqs. inverse2d/inverse3d/fast_inverse).
- * V_j drops the patch-boundary nodes on interior mesh faces and keeps those
- * on the domain boundary.  x, b: device [nrhs][ndofs(l)], not overlapping.
- * 1 <= level <= L. */
+ * With the Dirichlet kernels V_j drops the patch-boundary nodes on interior
+ * mesh faces and keeps those on the domain boundary; with the Full kernel it
+ * is the whole patch (see DGMG_SMOOTH_FULL).  x, b: device [nrhs][ndofs(l)],
+ * not overlapping.  1 <= level <= L. */
 dgmg_status dgmg_smooth_patch(dgmg_ctx* ctx, int level, double* x, const double* b,
                               int reverse_colours, int nrhs);
 dgmg_status dgmg_smooth_patch_f32(dgmg_ctx* ctx, int level, float* x, const float* b,
@@ -163,6 +173,21 @@ dgmg_status dgmg_vcycle_f32(dgmg_ctx* ctx, const float* b, float* x, int nrhs);
 dgmg_status dgmg_pcg_solve(dgmg_ctx* ctx, const double* b, double* x, int use_initial_guess,
                            double rtol, int maxit, int nrhs, int* iters, double* relres);
 
+/* Solve A_L x = b (one right-hand side) by GMRES right-preconditioned with
+ * one V-cycle per iteration, x0 = 0, no restart: the outer solver with which
+ * the paper measures its fractional iteration counts (Sec. 3.3, Tables 1
+ * and 2).  Flexible form (the preconditioned directions are stored), so the
+ * FP32 V-cycle is allowed too; Arnoldi by classical Gram-Schmidt with one
+ * re-orthogonalisation pass; Givens rotations on the host.  Stops when
+ * |r_m|_2 <= rtol |b|_2 (the Arnoldi residual estimate) or after maxit
+ * (1..1000) steps.  b, x: device [ndofs(L)].  *iters: steps taken;
+ * hist: host [maxit + 1] receiving |r_i| / |b| for i = 0..*iters.  The
+ * library keeps 2 maxit + 1 finest-level vectors for the Krylov basis (grown
+ * on demand, freed in dgmg_destroy).  Blocks until done; returns
+ * DGMG_ERR_NOT_CONVERGED (x, iters, hist filled) if maxit is reached. */
+dgmg_status dgmg_gmres_solve(dgmg_ctx* ctx, const double* b, double* x, double rtol, int maxit,
+                             int* iters, double* hist);
+
 /* out[j] = a_j . b_j for each right-hand side j (deterministic two-stage
  * reduction); a, b: device [nrhs][ndofs(level)]; out: host [nrhs].  Blocks
  * until the result is on the host.  Used for the coefficient gradient of the
@@ -173,11 +198,13 @@ dgmg_status dgmg_dot(dgmg_ctx* ctx, int level, const double* a, const double* b,
 /* Host-only, no context: the reference (h = 1, kappa = 1) 1-D data of the
  * fast diagonalisation (Sec. 3.2, eq. fast_inverse) for patch type
  * t = 0 (interior), 1 (touches x = 0), 2 (touches x = 1), 3 (both; coarsest
- * level).  S: host [(2k+2)*(2k+2)], S[p*(2k+2)+q] = entry of eigenvector q at
- * patch node p (zero rows for dropped nodes, zero columns beyond dim V_j);
- * lam: host [2k+2] generalised eigenvalues, +inf in unused slots.  The
- * eigenvectors satisfy S^T M S = I on the kept nodes. */
-dgmg_status dgmg_patch_eigen(int degree, double sigma, int type, double* S, double* lam);
+ * level) of the local space of smoother_variant (Dirichlet for EXACT and
+ * LOCAL, the whole patch for FULL).  S: host [(2k+2)*(2k+2)], S[p*(2k+2)+q] =
+ * entry of eigenvector q at patch node p (zero rows for dropped nodes, zero
+ * columns beyond dim V_j); lam: host [2k+2] generalised eigenvalues, +inf in
+ * unused slots.  The eigenvectors satisfy S^T M S = I on the kept nodes. */
+dgmg_status dgmg_patch_eigen(int degree, double sigma, int smoother_variant, int type, double* S,
+                             double* lam);
 
 /* Autotuner: for nrhs right-hand sides, time every workgroup shape (patches
  * per workgroup) and patch numbering (plain or XCD-aware) of the FP64

@@ -71,6 +71,9 @@ struct Level {
   double* x64 = nullptr;
   float* b32 = nullptr;
   float* x32 = nullptr;
+  // second copy of x for the Full smoother (levels >= 1), one per precision
+  double* alt64 = nullptr;
+  float* alt32 = nullptr;
 };
 
 template <int K, typename T>
@@ -94,6 +97,8 @@ void fill_tab(const dgmg::HostTables& H, std::vector<unsigned char>& out) {
     // kernels' reciprocal (estimate + Newton steps) returns ~0 without NaNs
     for (int i = 0; i < E; ++i)
       t->lam[ty][i] = std::isinf(H.lam[ty][i]) ? (T)(sizeof(T) == 8 ? 1e300 : 1e30) : (T)H.lam[ty][i];
+    for (int i = 0; i < E * E; ++i) t->Sf[ty][i] = (T)H.Sf[ty][i];
+    for (int i = 0; i < E; ++i) t->lamf[ty][i] = (T)H.lamf[ty][i];
   }
   for (int i = 0; i < E * n; ++i) t->P[i] = (T)H.P[i];
 }
@@ -147,6 +152,12 @@ struct dgmg_ctx {
   Tuning tune_smooth[2][21];  // per precision and level
   hipStream_t cap_stream = nullptr;
   std::vector<hipGraphExec_t> vc_graph;  // index nrhs - 1
+  // GMRES workspace (finest level, one right-hand side): Krylov basis V
+  // (gm_cap + 1 vectors), preconditioned directions Z (gm_cap vectors),
+  // device scalars and their pinned host mirror, partial sums
+  double *gm_V = nullptr, *gm_Z = nullptr, *gm_s = nullptr, *gm_partial = nullptr;
+  double* gm_h = nullptr;
+  int gm_cap = 0;
   std::string err;
 };
 
@@ -164,6 +175,12 @@ dgmg_status fail(dgmg_ctx* c, dgmg_status s, const std::string& msg) {
     hipError_t e_ = (expr);                                                           \
     if (e_ != hipSuccess)                                                             \
       return fail(ctx, DGMG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define RET_IF(expr)                       \
+  do {                                     \
+    dgmg_status s_ = (expr);               \
+    if (s_ != DGMG_OK) return s_;          \
   } while (0)
 
 template <typename T>
@@ -197,15 +214,25 @@ PatchGrid grid_colour0(const dgmg_ctx* c, int N) {
   return g;
 }
 
-PatchGrid grid_colour(const dgmg_ctx* c, int N, int colour) {
+// Patches of one colour: colour bit i = 0 takes the vertices v_i = 1, 3, ..,
+// N - 1 (cells lo_i = 0, 2, .., N - 2), bit 1 the vertices 2, 4, .., N - 2.
+// With `tiling` (Full smoother) bit 1 also takes the partial patches at
+// lo_i = -1 and N - 1, so that the colour's patches cover every cell once.
+PatchGrid grid_colour(const dgmg_ctx* c, int N, int colour, bool tiling = false) {
   PatchGrid g{};
   g.N = N;
   g.xcd_remap = xcd_remap_flag();
   g.npatch = 1;
   for (int i = 0; i < 3; ++i) {
     if (i < c->dim) {
-      g.off[i] = (colour >> i) & 1;
-      g.cnt[i] = g.off[i] ? (N - 2) / 2 : N / 2;
+      const int bit = (colour >> i) & 1;
+      if (bit && tiling) {
+        g.off[i] = -1;
+        g.cnt[i] = N / 2 + 1;
+      } else {
+        g.off[i] = bit;
+        g.cnt[i] = bit ? (N - 2) / 2 : N / 2;
+      }
     } else {
       g.off[i] = 0;
       g.cnt[i] = 1;
@@ -256,17 +283,43 @@ dgmg_status op_apply(dgmg_ctx* c, int l, const T* x, T* y, int nrhs) {
 }
 
 template <typename T>
+T*& lvalt(Level& L);
+template <>
+double*& lvalt<double>(Level& L) { return L.alt64; }
+template <>
+float*& lvalt<float>(Level& L) { return L.alt32; }
+
+template <typename T>
+dgmg_status ensure_alt(dgmg_ctx* c);
+
+// One smoothing step.  The Dirichlet kernels update x in place colour by
+// colour.  The Full kernel alternates between x and the level's second copy:
+// colour i reads one and writes the other, so after the 2^d colours (an even
+// number) the result is back in x.
+template <typename T>
 dgmg_status op_smooth(dgmg_ctx* c, int l, T* x, const T* b, int reverse, int nrhs) {
   const double sc = level_scale(c, l);
   const int nc = 1 << c->dim;
+  const bool full = c->variant == DGMG_SMOOTH_FULL;
+  T* cur = x;
+  T* other = nullptr;
+  if (full) {
+    RET_IF(ensure_alt<T>(c));
+    other = lvalt<T>(c->lv[l]);
+  }
   for (int i = 0; i < nc; ++i) {
     const int col = reverse ? nc - 1 - i : i;
-    PatchGrid g = grid_colour(c, c->lv[l].N, col);
+    PatchGrid g = grid_colour(c, c->lv[l].N, col, full);
     if (g.npatch == 0) continue;
     const auto& tu = c->tune_smooth[prec_index<T>()][l];
     g.xcd_remap = xcd_remap_flag(tu.remap);
-    HIPCHK(c, kset<T>(c).smooth[tu.shape](tab_of<T>(c), g, (T)sc, (T)(1.0 / sc), c->variant, x, b,
-                                          nrhs, c->lv[l].ndof, c->stream));
+    T* out = full ? other : cur;
+    HIPCHK(c, kset<T>(c).smooth[tu.shape](tab_of<T>(c), g, (T)sc, (T)(1.0 / sc), c->variant, cur, out,
+                                          b, nrhs, c->lv[l].ndof, c->stream));
+    if (full) {
+      other = cur;
+      cur = out;
+    }
   }
   return DGMG_OK;
 }
@@ -312,6 +365,19 @@ template <>
 double*& lvx<double>(Level& L) { return L.x64; }
 template <>
 float*& lvx<float>(Level& L) { return L.x32; }
+
+// Second copies of x on levels 1..L for the Full smoother.
+template <typename T>
+dgmg_status ensure_alt(dgmg_ctx* c) {
+  if (c->variant != DGMG_SMOOTH_FULL) return DGMG_OK;
+  for (int l = 1; l <= c->L; ++l) {
+    Level& L = c->lv[l];
+    hipError_t e = hipSuccess;
+    if (!lvalt<T>(L)) lvalt<T>(L) = dalloc<T>(L.ndof * c->nrhs_max, e);
+    if (e != hipSuccess) return fail(c, DGMG_ERR_ALLOC, "level vector allocation failed");
+  }
+  return DGMG_OK;
+}
 
 // Library-owned level vectors of precision T on levels [0, upto].
 template <typename T>
@@ -457,7 +523,8 @@ DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int sm
   if (c->ready) return fail(c, DGMG_ERR_STATE, "levels already set up");
   if (vcycle_precision != DGMG_FP64 && vcycle_precision != DGMG_FP32)
     return fail(c, DGMG_ERR_ARG, "vcycle_precision must be 64 or 32");
-  if (smoother_variant != DGMG_SMOOTH_EXACT && smoother_variant != DGMG_SMOOTH_LOCAL)
+  if (smoother_variant != DGMG_SMOOTH_EXACT && smoother_variant != DGMG_SMOOTH_LOCAL &&
+      smoother_variant != DGMG_SMOOTH_FULL)
     return fail(c, DGMG_ERR_ARG, "unknown smoother variant");
   if (nrhs_max < 1 || nrhs_max > 4096) return fail(c, DGMG_ERR_ARG, "nrhs_max out of range");
   c->prec = vcycle_precision;
@@ -487,6 +554,8 @@ DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int sm
   c->ready = true;
   if (vcycle_precision == DGMG_FP64) RET(ensure_levels<double>(c, c->L - 1));
   else RET(ensure_levels<float>(c, c->L));
+  RET(ensure_alt<double>(c));
+  if (vcycle_precision == DGMG_FP32) RET(ensure_alt<float>(c));
   return DGMG_OK;
 }
 
@@ -707,6 +776,159 @@ DGMG_API dgmg_status dgmg_pcg_solve(dgmg_ctx* c, const double* b, double* x, int
   return status;
 }
 
+namespace {
+
+void free_gmres(dgmg_ctx* c) {
+  hipFree(c->gm_V);
+  hipFree(c->gm_Z);
+  hipFree(c->gm_s);
+  hipFree(c->gm_partial);
+  if (c->gm_h) hipHostFree(c->gm_h);
+  c->gm_V = c->gm_Z = c->gm_s = c->gm_partial = c->gm_h = nullptr;
+  c->gm_cap = 0;
+}
+
+// Grow the GMRES workspace to cap steps, keeping the first keepV basis
+// vectors and keepZ directions (the basis grows with the iteration, so a
+// large maxit costs memory only when the iteration actually runs that long).
+dgmg_status ensure_gmres(dgmg_ctx* c, int cap, int keepV, int keepZ) {
+  if (cap <= c->gm_cap) return DGMG_OK;
+  const long long n = c->lv[c->L].ndof;
+  hipError_t e = hipSuccess;
+  double* V = dalloc<double>((long long)(cap + 1) * n, e);
+  double* Z = (e == hipSuccess) ? dalloc<double>((long long)cap * n, e) : nullptr;
+  double* sc = (e == hipSuccess) ? dalloc<double>(3LL * (cap + 2), e) : nullptr;
+  double* part = (e == hipSuccess) ? dalloc<double>((long long)(cap + 1) * dgmg::kRedBlocks, e) : nullptr;
+  double* hh = nullptr;
+  if (e == hipSuccess) e = hipHostMalloc((void**)&hh, sizeof(double) * 3 * (cap + 2));
+  if (e != hipSuccess) {
+    hipFree(V);
+    hipFree(Z);
+    hipFree(sc);
+    hipFree(part);
+    return fail(c, DGMG_ERR_ALLOC, "GMRES workspace allocation failed");
+  }
+  if (keepV > 0)
+    HIPCHK(c, hipMemcpyAsync(V, c->gm_V, sizeof(double) * n * keepV, hipMemcpyDeviceToDevice, c->stream));
+  if (keepZ > 0)
+    HIPCHK(c, hipMemcpyAsync(Z, c->gm_Z, sizeof(double) * n * keepZ, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  free_gmres(c);
+  c->gm_V = V;
+  c->gm_Z = Z;
+  c->gm_s = sc;
+  c->gm_partial = part;
+  c->gm_h = hh;
+  c->gm_cap = cap;
+  return DGMG_OK;
+}
+
+}  // namespace
+
+DGMG_API dgmg_status dgmg_gmres_solve(dgmg_ctx* c, const double* b, double* x, double rtol, int maxit,
+                                      int* iters, double* hist) {
+  RET(check_level(c, c ? c->L : 0, 0, 1));
+  if (!x || !b || !iters || !hist) return fail(c, DGMG_ERR_ARG, "null argument");
+  if (!(rtol > 0) || maxit < 1 || maxit > 1000)
+    return fail(c, DGMG_ERR_ARG, "rtol must be > 0 and 1 <= maxit <= 1000");
+  RET(ensure_gmres(c, maxit < 16 ? maxit : 16, 0, 0));
+  const long long n = c->lv[c->L].ndof;
+  hipStream_t s = c->stream;
+  // device scalars: cap + 1 first-pass coefficients h1, cap + 1 second-pass
+  // coefficients h2, |w|^2 (and |b|^2 at the start) nn; pinned mirror hh
+  int cap = 0;
+  double *h1 = nullptr, *h2 = nullptr, *nn = nullptr, *hh = nullptr;
+  auto bind = [&]() {
+    cap = c->gm_cap;
+    h1 = c->gm_s;
+    h2 = c->gm_s + (cap + 2);
+    nn = c->gm_s + 2 * (cap + 2);
+    hh = c->gm_h;
+  };
+  bind();
+  // |b|, V_0 = b / |b|
+  HIPCHK(c, dgmg::blas_dot2(b, b, nullptr, nullptr, n, 1, c->gm_partial, nullptr, nn, nullptr, s));
+  HIPCHK(c, hipMemcpyAsync(hh, nn, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  const double beta = std::sqrt(hh[0]);
+  if (!std::isfinite(beta)) return fail(c, DGMG_ERR_ARG, "right-hand side contains NaN/Inf");
+  *iters = 0;
+  hist[0] = 1.0;
+  RET(zero_vec<double>(c, x, n));
+  if (beta == 0) return DGMG_OK;
+  HIPCHK(c, dgmg::blas_normalise(c->gm_V, b, nn, n, s));
+  // Hessenberg matrix (column-major, (maxit + 1) x maxit), Givens rotations,
+  // and the rotated right-hand side g
+  std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0);
+  g[0] = beta;
+  int m = 0;
+  dgmg_status status = DGMG_ERR_NOT_CONVERGED;
+  for (int j = 0; j < maxit; ++j) {
+    if (j + 1 > c->gm_cap) {  // grow: keep v_0..v_j and z_0..z_{j-1}
+      const int want = 2 * c->gm_cap < maxit ? 2 * c->gm_cap : maxit;
+      RET(ensure_gmres(c, want, j + 1, j));
+      bind();
+    }
+    double* vj = c->gm_V + (long long)j * n;
+    double* zj = c->gm_Z + (long long)j * n;
+    // z_j = V(v_j) through the CG workspace (graph replay), w = A z_j in q
+    HIPCHK(c, hipMemcpyAsync(c->r, vj, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    RET(precondition_cg(c, 1));
+    HIPCHK(c, hipMemcpyAsync(zj, c->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    RET(op_apply<double>(c, c->L, zj, c->q, 1));
+    // classical Gram-Schmidt, twice: h = V^T w, w -= V h
+    HIPCHK(c, dgmg::blas_multi_dot(c->gm_V, c->q, n, j + 1, c->gm_partial, h1, s));
+    HIPCHK(c, dgmg::blas_multi_axpy(c->q, c->gm_V, h1, j + 1, -1.0, n, s));
+    HIPCHK(c, dgmg::blas_multi_dot(c->gm_V, c->q, n, j + 1, c->gm_partial, h2, s));
+    HIPCHK(c, dgmg::blas_multi_axpy(c->q, c->gm_V, h2, j + 1, -1.0, n, s));
+    HIPCHK(c, dgmg::blas_dot2(c->q, c->q, nullptr, nullptr, n, 1, c->gm_partial, nullptr, nn,
+                              nullptr, s));
+    HIPCHK(c, hipMemcpyAsync(hh, c->gm_s, sizeof(double) * 3 * (cap + 2), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    double* Hj = &H[(size_t)j * (maxit + 1)];
+    for (int i = 0; i <= j; ++i) Hj[i] = hh[i] + hh[cap + 2 + i];
+    const double w2 = hh[2 * (cap + 2)];
+    if (!std::isfinite(w2) || !(w2 >= 0)) return fail(c, DGMG_ERR_BREAKDOWN, "GMRES: non-finite Arnoldi scalar");
+    Hj[j + 1] = std::sqrt(w2);
+    if (w2 > 0 && j + 1 < maxit)
+      HIPCHK(c, dgmg::blas_normalise(c->gm_V + (long long)(j + 1) * n, c->q, nn, n, s));
+    // apply the previous rotations to the new column, then a new one
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
+      Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
+      Hj[i] = t;
+    }
+    const double den = std::hypot(Hj[j], Hj[j + 1]);
+    if (!(den > 0)) return fail(c, DGMG_ERR_BREAKDOWN, "GMRES: singular Hessenberg column");
+    cs[j] = Hj[j] / den;
+    sn[j] = Hj[j + 1] / den;
+    Hj[j] = den;
+    Hj[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    m = j + 1;
+    hist[m] = std::fabs(g[m]) / beta;
+    *iters = m;
+    if (hist[m] <= rtol || w2 == 0) {
+      status = DGMG_OK;
+      break;
+    }
+  }
+  // y = R^{-1} g (back substitution), x = Z y
+  std::vector<double> y(m);
+  for (int i = m - 1; i >= 0; --i) {
+    double sum = g[i];
+    for (int l = i + 1; l < m; ++l) sum -= H[(size_t)l * (maxit + 1) + i] * y[l];
+    y[i] = sum / H[(size_t)i * (maxit + 1) + i];
+  }
+  for (int i = 0; i < m; ++i) hh[i] = y[i];
+  HIPCHK(c, hipMemcpyAsync(h1, hh, sizeof(double) * m, hipMemcpyHostToDevice, s));
+  HIPCHK(c, dgmg::blas_multi_axpy(x, c->gm_Z, h1, m, 1.0, n, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (status != DGMG_OK) c->err = "maximum number of iterations reached";
+  return status;
+}
+
 DGMG_API dgmg_status dgmg_dot(dgmg_ctx* c, int level, const double* a, const double* b, int nrhs,
                               double* out) {
   RET(check_level(c, level, 0, nrhs));
@@ -881,14 +1103,19 @@ DGMG_API dgmg_status dgmg_autotune(dgmg_ctx* c, int nrhs, const char* cache_path
   return DGMG_OK;
 }
 
-DGMG_API dgmg_status dgmg_patch_eigen(int degree, double sigma, int type, double* S, double* lam) {
+DGMG_API dgmg_status dgmg_patch_eigen(int degree, double sigma, int smoother_variant, int type,
+                                      double* S, double* lam) {
   if (degree < 1 || degree > dgmg::kMaxDegree || !(sigma > 0) || type < 0 || type > 3 || !S || !lam)
+    return DGMG_ERR_ARG;
+  if (smoother_variant != DGMG_SMOOTH_EXACT && smoother_variant != DGMG_SMOOTH_LOCAL &&
+      smoother_variant != DGMG_SMOOTH_FULL)
     return DGMG_ERR_ARG;
   dgmg::HostTables H;
   const char* err = nullptr;
   if (!dgmg::build_host_tables(degree, sigma, H, &err)) return DGMG_ERR_ARG;
-  std::memcpy(S, H.S[type].data(), sizeof(double) * H.E * H.E);
-  std::memcpy(lam, H.lam[type].data(), sizeof(double) * H.E);
+  const bool full = smoother_variant == DGMG_SMOOTH_FULL;
+  std::memcpy(S, (full ? H.Sf : H.S)[type].data(), sizeof(double) * H.E * H.E);
+  std::memcpy(lam, (full ? H.lamf : H.lam)[type].data(), sizeof(double) * H.E);
   return DGMG_OK;
 }
 
@@ -906,6 +1133,8 @@ DGMG_API dgmg_status dgmg_destroy(dgmg_ctx* c) {
     hipFree(L.x64);
     hipFree(L.b32);
     hipFree(L.x32);
+    hipFree(L.alt64);
+    hipFree(L.alt32);
   }
   hipFree(c->tab64);
   hipFree(c->tab32);
@@ -917,6 +1146,7 @@ DGMG_API dgmg_status dgmg_destroy(dgmg_ctx* c) {
   hipFree(c->partial);
   hipFree(c->partial2);
   hipFree(c->active);
+  free_gmres(c);
   if (c->hbuf) hipHostFree(c->hbuf);
   if (c->hact) hipHostFree(c->hact);
   delete c;

@@ -21,6 +21,14 @@ hipError_t blas_update_xr(double* x, double* r, const double* p, const double* q
 hipError_t blas_update_p(double* p, const double* z, const double* rz_new, const double* rz_old,
                          const double* zq, const double* alpha, const int* active, int flexible,
                          long long n, int nrhs, hipStream_t s);
+// out[i] = V_i . w for the m vectors V_i = V + i n (partial: m * kRedBlocks).
+hipError_t blas_multi_dot(const double* V, const double* w, long long n, int m, double* partial,
+                          double* out, hipStream_t s);
+// w += sgn * sum_i coef[i] V_i (coef: device array of m doubles).
+hipError_t blas_multi_axpy(double* w, const double* V, const double* coef, int m, double sgn,
+                           long long n, hipStream_t s);
+// v = w / sqrt(nn[0]).
+hipError_t blas_normalise(double* v, const double* w, const double* nn, long long n, hipStream_t s);
 hipError_t blas_f64_to_f32(const double* a, float* b, long long n, hipStream_t s);
 hipError_t blas_f32_to_f64(const float* a, double* b, long long n, hipStream_t s);
 hipError_t blas_zero_f64(double* a, long long n, hipStream_t s);

@@ -24,17 +24,19 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // partial[r][blk] = sum over the block's grid-stride share of a_r . b_r
-// (and, if c != nullptr, partial2 = c_r . d_r)
+// (and, if c != nullptr, partial2 = c_r . d_r); vector r of a starts at
+// r * sa, of b at r * sb (sb = 0: one b against every a_r)
 __global__ void __launch_bounds__(kRedThreads)
 k_dot2(const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ c,
-       const double* __restrict__ d, long long n, double* __restrict__ partial,
-       double* __restrict__ partial2) {
+       const double* __restrict__ d, long long n, long long sa, long long sb,
+       double* __restrict__ partial, double* __restrict__ partial2) {
   __shared__ double sh[kRedThreads];
-  const long long off = (long long)blockIdx.y * n;
+  const long long off = (long long)blockIdx.y * sa;
+  const long long offb = (long long)blockIdx.y * sb;
   double s1 = 0.0, s2 = 0.0;
   const long long stride = (long long)gridDim.x * kRedThreads;
   for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
-    s1 += a[off + i] * b[off + i];
+    s1 += a[off + i] * b[offb + i];
     if (c) s2 += c[off + i] * d[off + i];
   }
   const double r1 = block_sum(s1, sh);
@@ -115,6 +117,28 @@ k_fill(T* __restrict__ a, T v, long long n) {
   for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) a[i] = v;
 }
 
+// w += sgn * sum_{i < m} coef[i] V_i  (V: m vectors at stride n)
+__global__ void __launch_bounds__(kRedThreads)
+k_multi_axpy(double* __restrict__ w, const double* __restrict__ V, const double* __restrict__ coef,
+             int m, double sgn, long long n) {
+  const long long stride = (long long)gridDim.x * kRedThreads;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) s += coef[j] * V[(long long)j * n + i];
+    w[i] += sgn * s;
+  }
+}
+
+// v = w / sqrt(nn[0]) (nn > 0 is checked by the host before the basis is used)
+__global__ void __launch_bounds__(kRedThreads)
+k_normalise(double* __restrict__ v, const double* __restrict__ w, const double* __restrict__ nn,
+            long long n) {
+  const double inv = 1.0 / sqrt(nn[0]);
+  const long long stride = (long long)gridDim.x * kRedThreads;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride)
+    v[i] = w[i] * inv;
+}
+
 // y = a - b  (residual r = b - A x)
 __global__ void __launch_bounds__(kRedThreads)
 k_sub(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y,
@@ -137,10 +161,30 @@ hipError_t blas_dot2(const double* a, const double* b, const double* c, const do
                      long long n, int nrhs, double* partial, double* partial2, double* out,
                      double* out2, hipStream_t s) {
   const int g = grid_for(n);
-  hipLaunchKernelGGL(k_dot2, dim3(g, nrhs), dim3(kRedThreads), 0, s, a, b, c, d, n, partial,
+  hipLaunchKernelGGL(k_dot2, dim3(g, nrhs), dim3(kRedThreads), 0, s, a, b, c, d, n, n, n, partial,
                      partial2);
   hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial, g, out);
   if (c) hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial2, g, out2);
+  return hipGetLastError();
+}
+
+hipError_t blas_multi_dot(const double* V, const double* w, long long n, int m, double* partial,
+                          double* out, hipStream_t s) {
+  const int g = grid_for(n);
+  hipLaunchKernelGGL(k_dot2, dim3(g, m), dim3(kRedThreads), 0, s, V, w, nullptr, nullptr, n, n, 0LL,
+                     partial, nullptr);
+  hipLaunchKernelGGL(k_finalize, dim3(m), dim3(kRedThreads), 0, s, partial, g, out);
+  return hipGetLastError();
+}
+
+hipError_t blas_multi_axpy(double* w, const double* V, const double* coef, int m, double sgn,
+                           long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(n)), dim3(kRedThreads), 0, s, w, V, coef, m, sgn, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_normalise(double* v, const double* w, const double* nn, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalise, dim3(grid_for(n)), dim3(kRedThreads), 0, s, v, w, nn, n);
   return hipGetLastError();
 }
 

@@ -18,8 +18,10 @@ constexpr int kSmoothShapes = 4;  // workgroup shapes x prefetch of b for smooth
 //   Lc  : 1-D SIPG cell block with interior faces on both sides
 //         K + sigma (e0 e0^T + e1 e1^T) + (e0 d0^T + d0 e0^T)/2 - (e1 d1^T + d1 e1^T)/2
 //   d0, d1 : phi'(0), phi'(1)
-//   S[t], lam[t] : fast-diagonalisation eigenpairs of patch type t, padded to E
-//         (unused eigenvalue slots hold a huge finite value)
+//   S[t], lam[t] : fast-diagonalisation eigenpairs of patch type t on the
+//         Dirichlet local space, padded to E (unused eigenvalue slots hold a
+//         huge finite value)
+//   Sf[t], lamf[t] : the same on the whole patch (Full kernel)
 //   P   : stacked prolongation, P[(o n + mu) n + nu] = phi_nu((xi_mu + o)/2)
 template <int K, typename T>
 struct Tab {
@@ -32,15 +34,19 @@ struct Tab {
   T sigma;
   T S[4][E * E];
   T lam[4][E];
+  T Sf[4][E * E];
+  T lamf[4][E];
   T P[E * n];
 };
 
 // The patches of one launch: patch m = (m_0, .., m_{D-1}), m_i < cnt[i], has
 // its lower-left cell at lo_i = off[i] + 2 m_i and covers cells lo_i, lo_i + 1.
+// The Full smoother's launches also carry the partial patches that complete
+// the tiling of the mesh (off = -1: lo_i = -1 or N - 1, one cell inside).
 struct PatchGrid {
   int N;       // cells per direction on the level
   int cnt[3];  // patches per direction
-  int off[3];  // 0 or 1: colour bit per direction
+  int off[3];  // -1, 0 or 1
   int npatch;  // product of cnt
   int xcd_remap;  // 1: give each XCD a contiguous range of patches
 };
@@ -55,8 +61,11 @@ struct KernelSet {
                          long long ndof, hipStream_t s);
   hipError_t (*mass)(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
                      long long ndof, hipStream_t s);
-  hipError_t (*smooth[kSmoothShapes])(const void* tab, PatchGrid g, T scale, T inv_scale, int local_variant,
-                          T* x, const T* b, int nrhs, long long ndof, hipStream_t s);
+  // variant: DGMG_SMOOTH_* of the context.  The Dirichlet kernels update x in
+  // place (xin is ignored); the Full kernel reads xin and writes xout.
+  hipError_t (*smooth[kSmoothShapes])(const void* tab, PatchGrid g, T scale, T inv_scale, int variant,
+                          const T* xin, T* xout, const T* b, int nrhs, long long ndof,
+                          hipStream_t s);
   hipError_t (*restrict_residual)(const void* tab, PatchGrid g, T scale, const T* x, const T* b,
                                   T* bc, int nrhs, long long ndof, long long ndof_c,
                                   hipStream_t s);

@@ -171,57 +171,69 @@ __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const
 }
 
 // Fast-diagonalisation contractions for patch type TY (padded S: rows p in
-// [PLO, PHI) and columns q < QN are the only non-zeros).
+// [PLO, PHI) and columns q < QN are the only non-zeros).  FULL selects the
+// whole-patch eigenpairs of the Full kernel (no padding).
 template <int TY> struct FDB;
 template <> struct FDB<0> { static constexpr int PLO = 1, PHI = E - 1, QN = E - 2; };
 template <> struct FDB<1> { static constexpr int PLO = 0, PHI = E - 1, QN = E - 1; };
 template <> struct FDB<2> { static constexpr int PLO = 1, PHI = E, QN = E - 1; };
 template <> struct FDB<3> { static constexpr int PLO = 0, PHI = E, QN = E; };
 
+template <typename T, bool FULL>
+__device__ __forceinline__ const T* fd_S(const Tab<K, T>* __restrict__ t, int ty) {
+  return FULL ? t->Sf[ty] : t->S[ty];
+}
+template <typename T, bool FULL>
+__device__ __forceinline__ const T* fd_lam(const Tab<K, T>* __restrict__ t, int ty) {
+  return FULL ? t->lamf[ty] : t->lam[ty];
+}
+
 // o[q] = sum_p S[p][q] v[p]
-template <typename T, int TY>
+template <typename T, int TY, bool FULL>
 __device__ __forceinline__ void line_St_t(const Tab<K, T>* __restrict__ t, const Line<T>& v, Line<T>& o) {
-  using B = FDB<TY>;
+  using B = FDB<FULL ? 3 : TY>;
+  const T* S = fd_S<T, FULL>(t, TY);
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     T s = T(0);
     if (q < B::QN) {
 #pragma unroll
-      for (int p = B::PLO; p < B::PHI; ++p) s += t->S[TY][p * E + q] * v.v[p];
+      for (int p = B::PLO; p < B::PHI; ++p) s += S[p * E + q] * v.v[p];
     }
     o.v[q] = s;
   }
 }
 // o[p] = sum_q S[p][q] v[q]
-template <typename T, int TY>
+template <typename T, int TY, bool FULL>
 __device__ __forceinline__ void line_S_t(const Tab<K, T>* __restrict__ t, const Line<T>& v, Line<T>& o) {
-  using B = FDB<TY>;
+  using B = FDB<FULL ? 3 : TY>;
+  const T* S = fd_S<T, FULL>(t, TY);
 #pragma unroll
   for (int p = 0; p < E; ++p) {
     T s = T(0);
     if (p >= B::PLO && p < B::PHI) {
 #pragma unroll
-      for (int q = 0; q < B::QN; ++q) s += t->S[TY][p * E + q] * v.v[q];
+      for (int q = 0; q < B::QN; ++q) s += S[p * E + q] * v.v[q];
     }
     o.v[p] = s;
   }
 }
-template <typename T>
+template <typename T, bool FULL>
 __device__ __forceinline__ void line_St(const Tab<K, T>* __restrict__ t, int ty, const Line<T>& v, Line<T>& o) {
   switch (ty) {
-    case 0: line_St_t<T, 0>(t, v, o); break;
-    case 1: line_St_t<T, 1>(t, v, o); break;
-    case 2: line_St_t<T, 2>(t, v, o); break;
-    default: line_St_t<T, 3>(t, v, o); break;
+    case 0: line_St_t<T, 0, FULL>(t, v, o); break;
+    case 1: line_St_t<T, 1, FULL>(t, v, o); break;
+    case 2: line_St_t<T, 2, FULL>(t, v, o); break;
+    default: line_St_t<T, 3, FULL>(t, v, o); break;
   }
 }
-template <typename T>
+template <typename T, bool FULL>
 __device__ __forceinline__ void line_S(const Tab<K, T>* __restrict__ t, int ty, const Line<T>& v, Line<T>& o) {
   switch (ty) {
-    case 0: line_S_t<T, 0>(t, v, o); break;
-    case 1: line_S_t<T, 1>(t, v, o); break;
-    case 2: line_S_t<T, 2>(t, v, o); break;
-    default: line_S_t<T, 3>(t, v, o); break;
+    case 0: line_S_t<T, 0, FULL>(t, v, o); break;
+    case 1: line_S_t<T, 1, FULL>(t, v, o); break;
+    case 2: line_S_t<T, 2, FULL>(t, v, o); break;
+    default: line_S_t<T, 3, FULL>(t, v, o); break;
   }
 }
 
@@ -690,43 +702,79 @@ k_mass(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restric
 // -------------------------------------------------------------- smoother
 // One colour of Alg. 1: local residual on the patch, then fast
 // diagonalisation x|V_j += (x)S (sum lambda)^{-1} (x)S^T r_j.
+//   MODE 1: Dirichlet kernel, consistent residual (b - A x)|V_j, in place;
+//   MODE 2: Dirichlet kernel, paper-literal residual (patch cells only), in place;
+//   MODE 3: Full kernel: V_j = the whole patch, r = (b - A x)|patch with x taken
+//           from xin, result written to xout.  Same-colour patches read each
+//           other's cells (face neighbours), so the colour reads one copy of x
+//           and writes the other; the launch also carries the partial patches
+//           at the mesh boundary, which copy their in-domain cells unchanged.
 template <typename T, int PPB, int MODE, bool PREFETCH>
 __global__ void __launch_bounds__(TPP * PPB)
-k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale, T* __restrict__ x,
-         const T* __restrict__ b, long long ndof) {
-  constexpr int PP = Smem<2, (D - 2) * 2 * NF>::per_patch;  // z-face traces only
+k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
+         const T* __restrict__ xin, T* __restrict__ xout, const T* __restrict__ b, long long ndof) {
+  constexpr bool FULL = (MODE == 3);
+  constexpr int OPM = FULL ? 0 : MODE;  // operator-pass mode (side data)
+  // operator face data (full rows) for the Full kernel, z-face traces only
+  // for the Dirichlet kernels
+  constexpr int PP = FULL ? Smem<2, (D - 1) * 2 * 2 * NF>::per_patch
+                          : Smem<2, (D - 2) * 2 * NF>::per_patch;
   __shared__ T smem[PPB * PP];
   const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
   const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
-  const bool active = pid < g.npatch;
+  const bool inrange = pid < g.npatch;
   T* A = smem + slot * PP;
   T* B = A + TS;
   T* ext = B + TS;
   const long long roff = (long long)blockIdx.y * ndof;
-  T* xr = x + roff;
+  T* xw = xout + roff;
+  const T* xr = (FULL ? xin : xout) + roff;
   const T* br = b + roff;
-  const PatchPos P = patch_pos(g, active ? pid : 0);
+  const PatchPos P = patch_pos(g, inrange ? pid : 0);
+  bool whole = true;
+#pragma unroll
+  for (int i = 0; i < D; ++i) whole = whole && P.lo[i] >= 0 && P.lo[i] + 1 < g.N;
+  const bool active = inrange && whole;
+  if (FULL && inrange && !whole) {
+    // partial patch: copy the rows of its in-domain cells
+    for (int i = lane; i < NL; i += TPP) {
+      const int py = i % E, pz = i / E;
+      const int cy = P.lo[1] + py / n;
+      const int cz = (D == 3) ? P.lo[2] + pz / n : 0;
+      if (cy < 0 || cy >= g.N || cz < 0 || cz >= g.N) continue;
+      if (D == 2 && pz > 0) continue;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int cx = P.lo[0] + c;
+        if (cx < 0 || cx >= g.N) continue;
+        const long long row = cell_index(g.N, cx, cy, cz) * NC + (py % n) * n + ((D == 3) ? (pz % n) * n * n : 0);
+#pragma unroll
+        for (int a = 0; a < n; ++a) xw[row + a] = xr[row + a];
+      }
+    }
+  }
   const int tyx = P.ty[0], tyy = P.ty[1], tyz = P.ty[2];
   Line<T> xl;  // the thread's x-line of x, kept for the final update
-  // y-face couplings of the thread's y-line, read early from global, and
-  // (PREFETCH) its line of b for the last operator pass: one memory round trip
-  // less on the critical path of a patch, one tile more in flight per patch
-  const Sides<T> ysd = active ? yline_sides_global<T, MODE>(t, xr, g.N, P, lane % E, lane / E)
-                              : Sides<T>{};
+  // y-face couplings of the thread's y-line, read early from global (Dirichlet
+  // kernels), and (PREFETCH) its line of b for the last operator pass: one
+  // memory round trip less on the critical path of a patch, one tile more in
+  // flight per patch
+  const Sides<T> ysd = (!FULL && active) ? yline_sides_global<T, OPM>(t, xr, g.N, P, lane % E, lane / E)
+                                         : Sides<T>{};
   Line<T> bline;
   if (PREFETCH && active) read_lastline<T>(br, g.N, P, lane, bline);
 
   // residual r = b - A x on the last pass, contracted with S^T of that direction
-  operator_passes<T, MODE>(t, xr, g.N, P, A, B, ext, lane, active, xl, ysd,
-                           [&](int l, int base, int stride, const Line<T>& v) {
-                             Line<T> r, o;
-                             if (PREFETCH) r = bline;
-                             else read_lastline<T>(br, g.N, P, l, r);
+  operator_passes<T, OPM>(t, xr, g.N, P, A, B, ext, lane, active, xl, ysd,
+                          [&](int l, int base, int stride, const Line<T>& v) {
+                            Line<T> r, o;
+                            if (PREFETCH) r = bline;
+                            else read_lastline<T>(br, g.N, P, l, r);
 #pragma unroll
-                             for (int p = 0; p < E; ++p) r.v[p] -= scale * v.v[p];
-                             line_St<T>(t, (D == 3) ? tyz : tyy, r, o);
-                             store_line(A, base, stride, o);
-                           });
+                            for (int p = 0; p < E; ++p) r.v[p] -= scale * v.v[p];
+                            line_St<T, FULL>(t, (D == 3) ? tyz : tyy, r, o);
+                            store_line(A, base, stride, o);
+                          });
   __syncthreads();
   if constexpr (D == 3) {
     // X1: S_x^T
@@ -736,7 +784,7 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale, T* 
         line_geom(0, i, base, stride);
         Line<T> v, o;
         load_line(A, base, stride, v);
-        line_St<T>(t, tyx, v, o);
+        line_St<T, FULL>(t, tyx, v, o);
         store_line(A, base, stride, o);
       }
     __syncthreads();
@@ -746,13 +794,14 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale, T* 
         const int qx = i % E, qz = i / E;
         int base, stride;
         line_geom(1, i, base, stride);
-        const T lt = t->lam[tyx][qx] + t->lam[tyz][qz];
+        const T* ly = fd_lam<T, FULL>(t, tyy);
+        const T lt = fd_lam<T, FULL>(t, tyx)[qx] + fd_lam<T, FULL>(t, tyz)[qz];
         Line<T> v, o;
         load_line(A, base, stride, v);
-        line_St<T>(t, tyy, v, o);
+        line_St<T, FULL>(t, tyy, v, o);
 #pragma unroll
-        for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(t->lam[tyy][q] + lt));
-        line_S<T>(t, tyy, o, v);
+        for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(ly[q] + lt));
+        line_S<T, FULL>(t, tyy, o, v);
         store_line(A, base, stride, v);
       }
     __syncthreads();
@@ -763,7 +812,7 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale, T* 
         line_geom(2, i, base, stride);
         Line<T> v, o;
         load_line(A, base, stride, v);
-        line_S<T>(t, tyz, v, o);
+        line_S<T, FULL>(t, tyz, v, o);
         store_line(A, base, stride, o);
       }
     __syncthreads();
@@ -774,13 +823,14 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale, T* 
         const int qy = i;
         int base, stride;
         line_geom(0, i, base, stride);
-        const T lt = t->lam[tyy][qy];
+        const T* lx = fd_lam<T, FULL>(t, tyx);
+        const T lt = fd_lam<T, FULL>(t, tyy)[qy];
         Line<T> v, o;
         load_line(A, base, stride, v);
-        line_St<T>(t, tyx, v, o);
+        line_St<T, FULL>(t, tyx, v, o);
 #pragma unroll
-        for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(t->lam[tyx][q] + lt));
-        line_S<T>(t, tyx, o, v);
+        for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(lx[q] + lt));
+        line_S<T, FULL>(t, tyx, o, v);
         store_line(A, base, stride, v);
       }
     __syncthreads();
@@ -791,7 +841,7 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale, T* 
         line_geom(1, i, base, stride);
         Line<T> v, o;
         load_line(A, base, stride, v);
-        line_S<T>(t, tyy, v, o);
+        line_S<T, FULL>(t, tyy, v, o);
         store_line(A, base, stride, o);
       }
     __syncthreads();
@@ -801,8 +851,9 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale, T* 
   if (active) {
     for (int i = lane; i < NL; i += TPP) {
       const int py = i % E, pz = i / E;
-      const bool keep_line = (py > 0 || (tyy & 1)) && (py < E - 1 || (tyy & 2)) &&
-                             (D == 2 || ((pz > 0 || (tyz & 1)) && (pz < E - 1 || (tyz & 2))));
+      const bool keep_line = FULL ||
+                             ((py > 0 || (tyy & 1)) && (py < E - 1 || (tyy & 2)) &&
+                              (D == 2 || ((pz > 0 || (tyz & 1)) && (pz < E - 1 || (tyz & 2)))));
       if (!keep_line) continue;
       int base, stride;
       line_geom(0, i, base, stride);
@@ -810,22 +861,22 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale, T* 
       load_line(A, base, stride, dl);
       if constexpr (D == 3) {
         Line<T> o;
-        line_S<T>(t, tyx, dl, o);
+        line_S<T, FULL>(t, tyx, dl, o);
         dl = o;
       }
-      // whole rows: the dropped end nodes of V_j are rewritten with their
-      // unchanged value (delta is exactly zero there), so no same-colour
-      // reader can observe a different value
+      // whole rows: the dropped end nodes of a Dirichlet V_j are rewritten
+      // with their unchanged value (delta is exactly zero there), so no
+      // same-colour reader can observe a different value
       const long long row0 = xrow_offset(g.N, P, py, pz);
       Line<T> nx;
 #pragma unroll
       for (int p = 0; p < E; ++p) nx.v[p] = xl.v[p] + dl.v[p];
-      if (!(tyx & 1)) nx.v[0] = xl.v[0];
-      if (!(tyx & 2)) nx.v[E - 1] = xl.v[E - 1];
+      if (!FULL && !(tyx & 1)) nx.v[0] = xl.v[0];
+      if (!FULL && !(tyx & 2)) nx.v[E - 1] = xl.v[E - 1];
 #pragma unroll
       for (int a = 0; a < n; ++a) {
-        xr[row0 + a] = nx.v[a];
-        xr[row0 + NC + a] = nx.v[n + a];
+        xw[row0 + a] = nx.v[a];
+        xw[row0 + NC + a] = nx.v[n + a];
       }
     }
   }
@@ -993,7 +1044,7 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
     line_geom(0, i, base, stride);
     Line<T> v, o;
     read_xline<T>(b + roff, xrow_offset(2, P, py, pz), v);
-    line_St_t<T, 3>(t, v, o);
+    line_St_t<T, 3, false>(t, v, o);
     store_line(tile, base, stride, o);
   }
   __syncthreads();
@@ -1005,14 +1056,14 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
       line_geom(dir, i, base, stride);
       Line<T> v, o;
       load_line(tile, base, stride, v);
-      line_St_t<T, 3>(t, v, o);
+      line_St_t<T, 3, false>(t, v, o);
       if (dir == D - 1) {
         const int qa = i % E, qb = i / E;
         T lt = t->lam[3][qa];
         if (D == 3) lt += t->lam[3][qb];
 #pragma unroll
         for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(t->lam[3][q] + lt));
-        line_S_t<T, 3>(t, o, v);
+        line_S_t<T, 3, false>(t, o, v);
         o = v;
       }
       store_line(tile, base, stride, o);
@@ -1027,7 +1078,7 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
       line_geom(dir, i, base, stride);
       Line<T> v, o;
       load_line(tile, base, stride, v);
-      line_S_t<T, 3>(t, v, o);
+      line_S_t<T, 3, false>(t, v, o);
       store_line(tile, base, stride, o);
     }
     __syncthreads();
@@ -1038,7 +1089,7 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
     line_geom(0, i, base, stride);
     Line<T> v, o;
     load_line(tile, base, stride, v);
-    line_S_t<T, 3>(t, v, o);
+    line_S_t<T, 3, false>(t, v, o);
     const long long row0 = roff + xrow_offset(2, P, py, pz);
 #pragma unroll
     for (int a = 0; a < n; ++a) {
@@ -1076,19 +1127,24 @@ hipError_t launch_mass(const void* tab, PatchGrid g, T scale, const T* x, T* y, 
                      (const Tab<K, T>*)tab, g, scale, x, y, ndof);
   return hipGetLastError();
 }
-// smoother shapes: bit 0 selects the workgroup shape, bit 1 the prefetch of b
+// smoother shapes: bit 0 selects the workgroup shape, bit 1 the prefetch of b;
+// variant 0 / 1 / 2: Dirichlet consistent / Dirichlet paper-literal / Full
 template <typename T, int V>
-hipError_t launch_smooth(const void* tab, PatchGrid g, T scale, T inv_scale, int local_variant,
-                         T* x, const T* b, int nrhs, long long ndof, hipStream_t s) {
+hipError_t launch_smooth(const void* tab, PatchGrid g, T scale, T inv_scale, int variant,
+                         const T* xin, T* xout, const T* b, int nrhs, long long ndof, hipStream_t s) {
   constexpr int PPB = Shape<(V & 1)>::PPB;
   constexpr bool PF = (V & 2) != 0;
   dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
-  if (local_variant)
-    hipLaunchKernelGGL((k_smooth<T, PPB, 2, PF>), grid, dim3(TPP * PPB), 0, s,
-                       (const Tab<K, T>*)tab, g, scale, inv_scale, x, b, ndof);
+  const Tab<K, T>* tb = (const Tab<K, T>*)tab;
+  if (variant == 2)
+    hipLaunchKernelGGL((k_smooth<T, PPB, 3, PF>), grid, dim3(TPP * PPB), 0, s, tb, g, scale,
+                       inv_scale, xin, xout, b, ndof);
+  else if (variant == 1)
+    hipLaunchKernelGGL((k_smooth<T, PPB, 2, PF>), grid, dim3(TPP * PPB), 0, s, tb, g, scale,
+                       inv_scale, xout, xout, b, ndof);
   else
-    hipLaunchKernelGGL((k_smooth<T, PPB, 1, PF>), grid, dim3(TPP * PPB), 0, s,
-                       (const Tab<K, T>*)tab, g, scale, inv_scale, x, b, ndof);
+    hipLaunchKernelGGL((k_smooth<T, PPB, 1, PF>), grid, dim3(TPP * PPB), 0, s, tb, g, scale,
+                       inv_scale, xout, xout, b, ndof);
   return hipGetLastError();
 }
 template <typename T>

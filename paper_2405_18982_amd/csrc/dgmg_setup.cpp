@@ -2,8 +2,8 @@
 // multigrid (Sec. 2.2, Sec. 3.2, Appendix A): Gauss-Lobatto nodes, Lagrange
 // basis, cell mass/stiffness, the 1-D SIPG cell block, the embedding
 // prolongation, and the fast-diagonalisation eigenpairs L S = M S Lambda of
-// the two-cell patch restricted to the Dirichlet local space, for each of the
-// four 1-D patch types.  Everything is computed at h = 1, kappa = 1; the
+// the two-cell patch restricted to the Dirichlet local space and on the whole
+// patch (Full kernel), for each of the four 1-D patch types.  Everything is computed at h = 1, kappa = 1; the
 // kernels scale by kappa h^(d-2).
 #include "dgmg_setup.h"
 
@@ -130,6 +130,60 @@ void jacobi_eigen(std::vector<double> A, int m, std::vector<double>& w, std::vec
   for (int i = 0; i < m; ++i) w[i] = A[i * m + i];
 }
 
+// Generalised eigenpairs L S = M S Lambda of the E x E patch matrices L, M
+// restricted to the node set keep, padded back to E: S[p*E + q] (zero rows
+// for dropped nodes, zero columns q >= |keep|), lam[q] (+inf unused).
+// Via M = C C^T: C^{-1} L C^{-T} = Q Lambda Q^T, S = C^{-T} Q (S^T M S = I).
+bool patch_eigenpairs(const std::vector<double>& L, const std::vector<double>& Mp, int E,
+                      const std::vector<int>& keep, std::vector<double>& Sout,
+                      std::vector<double>& lamout, const char** err) {
+  const int m = (int)keep.size();
+  std::vector<double> Lt(m * m), Mt(m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      Lt[i * m + j] = L[keep[i] * E + keep[j]];
+      Mt[i * m + j] = Mp[keep[i] * E + keep[j]];
+    }
+  std::vector<double> C;
+  if (!cholesky(Mt, m, C)) { *err = "patch mass matrix is not positive definite"; return false; }
+  std::vector<double> Y(m * m), Bm(m * m);
+  for (int col = 0; col < m; ++col)  // Y = C^{-1} L (forward substitution per column)
+    for (int i = 0; i < m; ++i) {
+      double s = Lt[i * m + col];
+      for (int l = 0; l < i; ++l) s -= C[i * m + l] * Y[l * m + col];
+      Y[i * m + col] = s / C[i * m + i];
+    }
+  for (int row = 0; row < m; ++row)  // B = Y C^{-T}: solve C B^T = Y^T row by row
+    for (int i = 0; i < m; ++i) {
+      double s = Y[row * m + i];
+      for (int l = 0; l < i; ++l) s -= C[i * m + l] * Bm[row * m + l];
+      Bm[row * m + i] = s / C[i * m + i];
+    }
+  for (int i = 0; i < m; ++i)  // symmetrise round-off
+    for (int j = 0; j < i; ++j) {
+      const double a = 0.5 * (Bm[i * m + j] + Bm[j * m + i]);
+      Bm[i * m + j] = Bm[j * m + i] = a;
+    }
+  std::vector<double> w, Q;
+  jacobi_eigen(Bm, m, w, Q);
+  for (int i = 0; i < m; ++i)
+    if (!(w[i] > 0.0)) { *err = "patch SIPG matrix is not positive definite (penalty too small)"; return false; }
+  std::vector<double> S(m * m);  // S = C^{-T} Q: back substitution with C^T per column of Q
+  for (int col = 0; col < m; ++col)
+    for (int i = m - 1; i >= 0; --i) {
+      double s = Q[i * m + col];
+      for (int l = i + 1; l < m; ++l) s -= C[l * m + i] * S[l * m + col];
+      S[i * m + col] = s / C[i * m + i];
+    }
+  Sout.assign(E * E, 0.0);
+  lamout.assign(E, std::numeric_limits<double>::infinity());
+  for (int q = 0; q < m; ++q) {
+    lamout[q] = w[q];
+    for (int i = 0; i < m; ++i) Sout[keep[i] * E + q] = S[i * m + q];
+  }
+  return true;
+}
+
 }  // namespace
 
 std::vector<double> gll_nodes01(int k) {
@@ -229,53 +283,11 @@ bool build_host_tables(int k, double sigma, HostTables& T, const char** err) {
       const bool drop = (p == 0 && !(t & 1)) || (p == E - 1 && !(t & 2));
       if (!drop) keep.push_back(p);
     }
-    const int m = (int)keep.size();
-    std::vector<double> Lt(m * m), Mt(m * m);
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) {
-        Lt[i * m + j] = L[keep[i] * E + keep[j]];
-        Mt[i * m + j] = Mp[keep[i] * E + keep[j]];
-      }
-    // generalised problem L S = M S Lambda via M = C C^T:
-    // C^{-1} L C^{-T} = Q Lambda Q^T, S = C^{-T} Q (so S^T M S = I)
-    std::vector<double> C;
-    if (!cholesky(Mt, m, C)) { *err = "patch mass matrix is not positive definite"; return false; }
-    std::vector<double> Y(m * m), Bm(m * m);
-    for (int col = 0; col < m; ++col)  // Y = C^{-1} L (forward substitution per column)
-      for (int i = 0; i < m; ++i) {
-        double s = Lt[i * m + col];
-        for (int l = 0; l < i; ++l) s -= C[i * m + l] * Y[l * m + col];
-        Y[i * m + col] = s / C[i * m + i];
-      }
-    for (int row = 0; row < m; ++row)  // B = Y C^{-T}: solve C B^T = Y^T row by row
-      for (int i = 0; i < m; ++i) {
-        double s = Y[row * m + i];
-        for (int l = 0; l < i; ++l) s -= C[i * m + l] * Bm[row * m + l];
-        Bm[row * m + i] = s / C[i * m + i];
-      }
-    for (int i = 0; i < m; ++i)  // symmetrise round-off
-      for (int j = 0; j < i; ++j) {
-        const double a = 0.5 * (Bm[i * m + j] + Bm[j * m + i]);
-        Bm[i * m + j] = Bm[j * m + i] = a;
-      }
-    std::vector<double> w, Q;
-    jacobi_eigen(Bm, m, w, Q);
-    for (int i = 0; i < m; ++i)
-      if (!(w[i] > 0.0)) { *err = "patch SIPG matrix is not positive definite (penalty too small)"; return false; }
-    // S = C^{-T} Q: back substitution with C^T per column of Q
-    std::vector<double> S(m * m);
-    for (int col = 0; col < m; ++col)
-      for (int i = m - 1; i >= 0; --i) {
-        double s = Q[i * m + col];
-        for (int l = i + 1; l < m; ++l) s -= C[l * m + i] * S[l * m + col];
-        S[i * m + col] = s / C[i * m + i];
-      }
-    T.S[t].assign(E * E, 0.0);
-    T.lam[t].assign(E, std::numeric_limits<double>::infinity());
-    for (int q = 0; q < m; ++q) {
-      T.lam[t][q] = w[q];
-      for (int i = 0; i < m; ++i) T.S[t][keep[i] * E + q] = S[i * m + q];
-    }
+    if (!patch_eigenpairs(L, Mp, E, keep, T.S[t], T.lam[t], err)) return false;
+    // Full kernel: every node of the two cells
+    std::vector<int> all(E);
+    for (int p = 0; p < E; ++p) all[p] = p;
+    if (!patch_eigenpairs(L, Mp, E, all, T.Sf[t], T.lamf[t], err)) return false;
   }
   return true;
 }

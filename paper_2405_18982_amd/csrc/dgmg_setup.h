@@ -13,10 +13,14 @@ struct HostTables {
   std::vector<double> d0, d1;  // phi'(0), phi'(1)
   std::vector<double> Lc;      // interior-type SIPG cell block, n x n
   std::vector<double> P;       // stacked prolongation, E x n
-  // fast diagonalisation per patch type t = 0..3, padded to E:
+  // fast diagonalisation on the Dirichlet local space per patch type t = 0..3,
+  // padded to E:
   // S[t][p*E + q], lam[t][q] (+inf in unused slots)
   std::vector<double> S[4];
   std::vector<double> lam[4];
+  // the same on the whole two-cell patch (Full kernel; every slot used)
+  std::vector<double> Sf[4];
+  std::vector<double> lamf[4];
 };
 
 // Builds every table; returns false (with a message) if a factorisation fails,

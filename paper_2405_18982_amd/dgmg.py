@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgmg.so")
 
 FP64, FP32 = 64, 32
-SMOOTH_EXACT, SMOOTH_LOCAL = 0, 1
+SMOOTH_EXACT, SMOOTH_LOCAL, SMOOTH_FULL = 0, 1, 2
 
 STATUS = {
     0: "DGMG_OK", -1: "DGMG_ERR_ARG", -2: "DGMG_ERR_ALLOC", -3: "DGMG_ERR_HIP",
@@ -48,9 +48,10 @@ SIGNATURES = {
     "dgmg_vcycle": (_I, [_P, _P, _P, _I]),
     "dgmg_vcycle_f32": (_I, [_P, _P, _P, _I]),
     "dgmg_pcg_solve": (_I, [_P, _P, _P, _I, _D, _I, _I, _P, _P]),
+    "dgmg_gmres_solve": (_I, [_P, _P, _P, _D, _I, _P, _P]),
     "dgmg_dot": (_I, [_P, _I, _P, _P, _I, _P]),
     "dgmg_autotune": (_I, [_P, _I, _c.c_char_p, _P, _I]),
-    "dgmg_patch_eigen": (_I, [_I, _D, _I, _P, _P]),
+    "dgmg_patch_eigen": (_I, [_I, _D, _I, _I, _P, _P]),
     "dgmg_last_error": (_c.c_char_p, [_P]),
     "dgmg_destroy": (_I, [_P]),
 }
@@ -83,12 +84,13 @@ class DGMGError(RuntimeError):
         self.status = status
 
 
-def patch_eigen(k, sigma, ptype):
-    """Host-only reference 1-D fast-diagonalisation data (S, lam) of a patch type."""
+def patch_eigen(k, sigma, ptype, variant=SMOOTH_EXACT):
+    """Host-only reference 1-D fast-diagonalisation data (S, lam) of a patch
+    type for the local space of a smoother variant."""
     E = 2 * (k + 1)
     S = np.zeros(E * E)
     lam = np.zeros(E)
-    st = lib().dgmg_patch_eigen(k, sigma, ptype, S.ctypes.data, lam.ctypes.data)
+    st = lib().dgmg_patch_eigen(k, sigma, variant, ptype, S.ctypes.data, lam.ctypes.data)
     if st != 0:
         raise DGMGError(st, "dgmg_patch_eigen failed")
     return S.reshape(E, E), lam
@@ -300,6 +302,24 @@ class Problem:
             return out, iters, relres
         self._check(st)
         return out, iters, relres
+
+    def gmres(self, b, rtol=1e-8, maxit=50, out=None, raise_on_nonconvergence=True):
+        """Right-preconditioned GMRES from x0 = 0 (one right-hand side);
+        returns (x, iterations, residual history |r_i|/|b|, i = 0..iterations)."""
+        torch = _torch()
+        pb, nr = self._vec(b, self.L, torch.float64)
+        if nr != 1:
+            raise ValueError("gmres takes one right-hand side")
+        out = torch.empty_like(b) if out is None else out
+        px, _ = self._vec(out, self.L, torch.float64)
+        it = ctypes.c_int(0)
+        hist = np.zeros(int(maxit) + 1)
+        self._sync_stream()
+        st = lib().dgmg_gmres_solve(self._ctx, pb, px, float(rtol), int(maxit), ctypes.byref(it),
+                                    hist.ctypes.data)
+        if not (st == -4 and not raise_on_nonconvergence):
+            self._check(st)
+        return out, it.value, hist[: it.value + 1].copy()
 
     def close(self):
         if self._ctx:

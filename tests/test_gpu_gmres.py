@@ -1,0 +1,85 @@
+"""GPU parity of the right-preconditioned GMRES (Sec. 3.3) with every smoother
+variant against the oracle's GMRES on the same load (f = 1, built by the
+oracle): the same number of steps, the residual history step by step, the
+fractional iteration count nu and the solution."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.multigrid import Hierarchy, fractional_iterations, gmres
+from oracle.rhs import load_vector
+from paper_2405_18982_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_18982_amd import dgmg  # noqa: E402
+
+VARIANTS = {"exact": dgmg.SMOOTH_EXACT, "local": dgmg.SMOOTH_LOCAL, "full": dgmg.SMOOTH_FULL}
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def one(X):
+    return np.ones(X.shape[0])
+
+
+@pytest.mark.parametrize("variant", ["exact", "local", "full"])
+@pytest.mark.parametrize("dim,k,L", [(2, 2, 2), (2, 5, 3), (3, 3, 2), (3, 4, 1)])
+def test_gmres_history_and_nu_match_oracle(dim, k, L, variant):
+    note(f"gmres d={dim} k={k} L={L} {variant}")
+    sigma = 2.0 * k * (k + 1)  # the paper's penalty for the iteration tables
+    prob = dgmg.Problem(dim, k, L, sigma=sigma, variant=VARIANTS[variant])
+    N = 2 ** (L + 1)
+    b = load_vector(dim, k, N, one)
+    x, m, hist = prob.gmres(torch.from_numpy(b).cuda(), rtol=1e-8, maxit=60)
+    X = x.cpu().numpy()
+    prob.close()
+    H = Hierarchy(dim, k, L, sigma, mode=variant)
+    xo, mo, ho = gmres(H.apply[L], H.vcycle, b, rtol=1e-8, maxit=60)
+    assert m == mo, (m, mo)
+    ho = np.array(ho)
+    assert np.all(np.abs(hist - ho) <= 1e-9 + 1e-6 * ho), np.c_[hist, ho]
+    nu, nuo = fractional_iterations(hist), fractional_iterations(ho)
+    assert abs(nu - nuo) <= 1e-3, (nu, nuo)
+    assert np.linalg.norm(X - xo) <= 1e-9 * np.linalg.norm(xo)
+    note(f"  steps {m}, nu {nu:.3f} (oracle {nuo:.3f})")
+
+
+def test_gmres_mixed_precision_vcycle():
+    note("gmres mixed")
+    dim, k, L = 3, 3, 2
+    sigma = 2.0 * k * (k + 1)
+    N = 2 ** (L + 1)
+    b = load_vector(dim, k, N, one)
+    nus = {}
+    for prec in (64, 32):
+        prob = dgmg.Problem(dim, k, L, sigma=sigma, precision=prec)
+        x, m, hist = prob.gmres(torch.from_numpy(b).cuda(), rtol=1e-8, maxit=60)
+        prob.close()
+        assert hist[-1] <= 1e-8
+        nus[prec] = fractional_iterations(hist)
+    assert abs(nus[64] - nus[32]) <= 0.05, nus
+
+
+def test_gmres_reports_nonconvergence_and_zero_rhs():
+    note("gmres error paths")
+    prob = dgmg.Problem(2, 2, 2)
+    b = torch.from_numpy(inputs.uniform(61, prob.ndofs())).cuda()
+    with pytest.raises(dgmg.DGMGError) as e:
+        prob.gmres(b, rtol=1e-14, maxit=2)
+    assert e.value.status == -4
+    x, m, hist = prob.gmres(b, rtol=1e-14, maxit=2, raise_on_nonconvergence=False)
+    assert m == 2 and len(hist) == 3 and hist[0] == 1.0 and hist[2] < hist[1] < 1.0
+    z, m, hist = prob.gmres(torch.zeros_like(b))
+    assert m == 0 and float(torch.abs(z).max()) == 0.0
+    with pytest.raises(dgmg.DGMGError):
+        prob.gmres(b, maxit=0)
+    prob.close()

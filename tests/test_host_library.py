@@ -101,3 +101,11 @@ def test_patch_eigenpairs_match_oracle(k, sigma_rule):
             assert np.allclose(Sk.T @ Mt @ Sk, np.eye(m), atol=1e-11)
             Linv = Sk @ np.diag(1.0 / lam[:m]) @ Sk.T
             assert np.abs(Linv @ Lt - np.eye(m)).max() < 1e-10
+            # Full kernel: the whole patch, every slot used
+            Sf, lamf = dgmg.patch_eigen(k, sigma, t, dgmg.SMOOTH_FULL)
+            E = 2 * (k + 1)
+            assert np.all(np.isfinite(lamf)) and np.all(lamf > 0)
+            Lp, Mp = fd.Lpatch[t] * h, fd.Mpatch[t] / h
+            assert np.allclose(Sf.T @ Mp @ Sf, np.eye(E), atol=1e-11)
+            Lfinv = Sf @ np.diag(1.0 / lamf) @ Sf.T
+            assert np.abs(Lfinv @ Lp - np.eye(E)).max() < 1e-10
