@@ -56,7 +56,7 @@ class Hierarchy:
 
     def smooth(self, l, x, b, order):
         if self.dense:
-            return smooth_dense(self.A[l], x, b, self.ps[l], order, self.mode)
+            return smooth_dense(self.A[l], x, b, self.ps[l], order, self.mode, self.kappa)
         return self.smoothers[l].step(x, b, order)
 
     def _round(self, v):

@@ -40,12 +40,14 @@ import itertools
 import numpy as np
 import scipy.linalg as sla
 
-from .patches import PatchSet, clamped_basis_1d, kept_1d, patch_type_1d
+from .basis import Basis1D
+from .patches import PatchSet, _tiles_vectorised, clamped_basis_1d, kept_1d, patch_type_1d
 from .sipg import KronApply, sipg_1d
 
 
-def smooth_dense(A, x, b, ps, order, mode="exact"):
-    """Sequential by-definition smoothing step (in place on a copy of x)."""
+def smooth_dense(A, x, b, ps, order, mode="exact", kappa=1.0):
+    """Sequential by-definition smoothing step (in place on a copy of x); kappa
+    is the coefficient A was built with (the 'local' residual needs it)."""
     x = np.array(x, dtype=np.float64, copy=True)
     A = A.tocsr()
     for c in order:
@@ -70,7 +72,8 @@ def smooth_dense(A, x, b, ps, order, mode="exact"):
                 r = b[V] - A[V] @ x
             elif mode == "local":
                 Vb = ps.vbar(j)
-                r = b[V] - A[V][:, Vb] @ x[Vb]
+                T = outer_face_consistency(ps.d, ps.k, ps.N, ps.verts[j], kappa)[ps.masks[j].reshape(-1)]
+                r = b[V] - A[V][:, Vb] @ x[Vb] - T @ x[Vb]
             else:
                 raise ValueError(mode)
             Ajj = A[V][:, V].toarray()
@@ -78,11 +81,45 @@ def smooth_dense(A, x, b, ps, order, mode="exact"):
     return x
 
 
+def outer_face_consistency(d, k, N, v, kappa=1.0):
+    """T[test, trial] = kappa/2 int_F u_P (n_P . grad v_P) summed over the faces
+    F of patch v that lie inside the domain on the patch boundary, for u, v in
+    the patch cell P next to F (n_P its outward normal): the inside half of
+    the SIPG term -[[u]].{grad v}, which the global matrix carries with the
+    opposite sign.  Dense over the patch tile in tile order, integrated by
+    the face quadrature of the operator assembly."""
+    from .sipg import _face_tabulation
+    n = k + 1
+    nl = n ** d
+    E = 2 * n
+    tile = _tiles_vectorised(d, k, N, np.array([v]))[0].reshape(-1)
+    pos = {int(g): p for p, g in enumerate(tile)}
+    T = np.zeros((E ** d, E ** d))
+    for i in range(d):
+        for side in (0, 1):
+            c_i = v[i] - 1 if side == 0 else v[i]  # patch layer next to that face
+            if (side == 0 and c_i == 0) or (side == 1 and c_i == N - 1):
+                continue  # domain boundary: Nitsche terms stay
+            val, grad, wf = _face_tabulation(d, k, N, i, side)
+            nrm = np.zeros(d)
+            nrm[i] = -1.0 if side == 0 else 1.0
+            blk = 0.5 * kappa * np.einsum("g,gbq,aq,q->ba", nrm, grad, val, wf)
+            for rest in itertools.product(*[(v[m] - 1, v[m]) for m in range(d) if m != i]):
+                cc = list(rest)
+                cc.insert(i, c_i)
+                cell = sum(cc[m] * N ** m for m in range(d))
+                idx = np.array([pos[cell * nl + a] for a in range(nl)])
+                T[np.ix_(idx, idx)] += blk
+    return T
+
+
 class PatchFD:
     """1-D patch matrices and their generalised eigenpairs for every patch
     type along one direction (interior, touching x=0, touching x=1, both):
     S, lam on the Dirichlet local space, Sf, lamf on the whole patch (Full
-    kernel), Sc = C S_C, lamc on the clamped space with basis C."""
+    kernel), Sc = C S_C, lamc on the clamped space with basis C; Llit the
+    patch matrix of the paper's Dirichlet residual (interior-end consistency
+    halves removed)."""
 
     def __init__(self, k, N, sigma, kappa=1.0):
         M, L = sipg_1d(k, N, sigma)
@@ -91,7 +128,9 @@ class PatchFD:
         self.k, self.N = k, N
         self.S, self.lam, self.Mt, self.Lt, self.keep = {}, {}, {}, {}, {}
         self.Mpatch, self.Lpatch, self.Sf, self.lamf = {}, {}, {}, {}
-        self.Sc, self.lamc = {}, {}
+        self.Sc, self.lamc, self.Llit = {}, {}, {}
+        bs = Basis1D(k)
+        h = 1.0 / N
         for vi in range(1, N):
             t = patch_type_1d(N, vi)
             if t in self.S:
@@ -104,6 +143,12 @@ class PatchFD:
             self.S[t], self.lam[t] = S, lam
             self.Mt[t], self.Lt[t], self.keep[t] = Mt, Lt, keep
             self.Mpatch[t], self.Lpatch[t] = Mp, Lp
+            Ll = Lp.copy()
+            if not t & 1:  # left end inside the domain: drop +1/2 v'(x+) u(x+)
+                Ll[:n, 0] -= kappa * 0.5 * bs.d0 / h
+            if not t & 2:  # right end: drop -1/2 v'(x-) u(x-)
+                Ll[n:, 2 * n - 1] += kappa * 0.5 * bs.d1 / h
+            self.Llit[t] = Ll
             self.lamf[t], self.Sf[t] = sla.eigh(Lp, Mp)
             C = clamped_basis_1d(k, t)
             if C.shape[1] > 0:
@@ -186,7 +231,7 @@ class FDSmoother:
                     for dirn in range(d):
                         T = X
                         for i in range(d):
-                            mat = self.fd.Lpatch[types[i]] if i == dirn else self.fd.Mpatch[types[i]]
+                            mat = self.fd.Llit[types[i]] if i == dirn else self.fd.Mpatch[types[i]]
                             T = _along(mat, T, d - i)
                         AX += T
                     R = b[sub] - AX[(slice(None),) + np.ix_(*ks)]
