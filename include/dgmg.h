@@ -64,16 +64,25 @@ enum { DGMG_FP64 = 64, DGMG_FP32 = 32 };
  * EXACT uses (b - A x) restricted to V_j, i.e. it adds the coupling of V_j to
  *   the traces of the face-neighbour cells outside the patch; the smoother is
  *   then an exact multiplicative subspace correction and the V-cycle symmetric.
- * LOCAL is the paper-literal kernel: r_j = b|V_j - A[V_j, Vbar_j] x|Vbar_j with
- *   Vbar_j the patch cells only (inconsistent residual; not for CG).
+ * LOCAL is the paper's kernel with its inconsistent residual: only the patch
+ *   cells are read and, on the patch's interior outer faces, the consistency
+ *   term -[[u]].{grad v} of the form (which does not vanish on V_j) is left
+ *   out altogether, so the residual is off by the jump of u there (not for
+ *   CG: the smoother is not symmetric).
  * FULL is the Full kernel: V_j = every node of the patch cells.  Its domain of
  *   dependence reaches into face-neighbour cells that other patches of the
  *   same colour update, so the residual is taken once per colour (the global
  *   update of Sec. 3.1): every patch of a colour corrects from b - A x of the
  *   colour's entry state (additive inside a colour, multiplicative across
  *   colours; the V-cycle stays symmetric).  The library keeps a second copy of
- *   x per level for it. */
-enum { DGMG_SMOOTH_EXACT = 0, DGMG_SMOOTH_LOCAL = 1, DGMG_SMOOTH_FULL = 2 };
+ *   x per level for it.
+ * CLAMPED is the clamped kernel: V_j = patch functions whose value and normal
+ *   derivative vanish on the patch faces inside the domain (faces on the
+ *   domain boundary stay free), (2k-2)^d unknowns for an interior patch.  The
+ *   face terms coupling V_j to outside cells vanish on this space, so the
+ *   exact local residual needs only the patch cells.  Needs degree >= 3 (for
+ *   k = 2 the clamped spaces do not cover Q_k and the V-cycle is singular). */
+enum { DGMG_SMOOTH_EXACT = 0, DGMG_SMOOTH_LOCAL = 1, DGMG_SMOOTH_FULL = 2, DGMG_SMOOTH_CLAMPED = 3 };
 
 /* Create a context for the problem above.  dim in {2,3}; 1 <= degree <= 7;
  * 1 <= finest_level with ndofs(L) < 2^40; penalty_sigma > 0 (the operator is
@@ -85,7 +94,8 @@ dgmg_status dgmg_setup_mesh(int dim, int degree, int finest_level, double penalt
 
 /* Allocate device tables and workspaces.  vcycle_precision: DGMG_FP64, or
  * DGMG_FP32 for the mixed form (V-cycle in FP32 inside FP64 CG, Sec. 5.2).
- * smoother_variant: DGMG_SMOOTH_EXACT, DGMG_SMOOTH_LOCAL or DGMG_SMOOTH_FULL.
+ * smoother_variant: DGMG_SMOOTH_EXACT, DGMG_SMOOTH_LOCAL, DGMG_SMOOTH_FULL or
+ * DGMG_SMOOTH_CLAMPED.
  * nrhs_max >= 1 bounds the nrhs of every later call.  hip_stream: hipStream_t
  * or NULL. */
 dgmg_status dgmg_setup_levels(dgmg_ctx* ctx, int vcycle_precision, int smoother_variant,
@@ -199,10 +209,11 @@ dgmg_status dgmg_dot(dgmg_ctx* ctx, int level, const double* a, const double* b,
  * fast diagonalisation (Sec. 3.2, eq. fast_inverse) for patch type
  * t = 0 (interior), 1 (touches x = 0), 2 (touches x = 1), 3 (both; coarsest
  * level) of the local space of smoother_variant (Dirichlet for EXACT and
- * LOCAL, the whole patch for FULL).  S: host [(2k+2)*(2k+2)], S[p*(2k+2)+q] =
- * entry of eigenvector q at patch node p (zero rows for dropped nodes, zero
- * columns beyond dim V_j); lam: host [2k+2] generalised eigenvalues, +inf in
- * unused slots.  The eigenvectors satisfy S^T M S = I on the kept nodes. */
+ * LOCAL, the whole patch for FULL, the clamped space for CLAMPED).  S: host
+ * [(2k+2)*(2k+2)], S[p*(2k+2)+q] = value at patch node p of eigenvector q
+ * (zero rows for dropped nodes, zero columns beyond dim V_j); lam: host [2k+2]
+ * generalised eigenvalues, +inf in unused slots.  The eigenvectors satisfy
+ * S^T M S = I. */
 dgmg_status dgmg_patch_eigen(int degree, double sigma, int smoother_variant, int type, double* S,
                              double* lam);
 

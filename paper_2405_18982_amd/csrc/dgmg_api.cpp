@@ -99,6 +99,9 @@ void fill_tab(const dgmg::HostTables& H, std::vector<unsigned char>& out) {
       t->lam[ty][i] = std::isinf(H.lam[ty][i]) ? (T)(sizeof(T) == 8 ? 1e300 : 1e30) : (T)H.lam[ty][i];
     for (int i = 0; i < E * E; ++i) t->Sf[ty][i] = (T)H.Sf[ty][i];
     for (int i = 0; i < E; ++i) t->lamf[ty][i] = (T)H.lamf[ty][i];
+    for (int i = 0; i < E * E; ++i) t->Sc[ty][i] = (T)H.Sc[ty][i];
+    for (int i = 0; i < E; ++i)
+      t->lamc[ty][i] = std::isinf(H.lamc[ty][i]) ? (T)(sizeof(T) == 8 ? 1e300 : 1e30) : (T)H.lamc[ty][i];
   }
   for (int i = 0; i < E * n; ++i) t->P[i] = (T)H.P[i];
 }
@@ -524,8 +527,10 @@ DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int sm
   if (vcycle_precision != DGMG_FP64 && vcycle_precision != DGMG_FP32)
     return fail(c, DGMG_ERR_ARG, "vcycle_precision must be 64 or 32");
   if (smoother_variant != DGMG_SMOOTH_EXACT && smoother_variant != DGMG_SMOOTH_LOCAL &&
-      smoother_variant != DGMG_SMOOTH_FULL)
+      smoother_variant != DGMG_SMOOTH_FULL && smoother_variant != DGMG_SMOOTH_CLAMPED)
     return fail(c, DGMG_ERR_ARG, "unknown smoother variant");
+  if (smoother_variant == DGMG_SMOOTH_CLAMPED && c->k < 3)
+    return fail(c, DGMG_ERR_ARG, "the clamped kernel needs degree >= 3");
   if (nrhs_max < 1 || nrhs_max > 4096) return fail(c, DGMG_ERR_ARG, "nrhs_max out of range");
   c->prec = vcycle_precision;
   c->variant = smoother_variant;
@@ -865,7 +870,14 @@ DGMG_API dgmg_status dgmg_gmres_solve(dgmg_ctx* c, const double* b, double* x, d
   dgmg_status status = DGMG_ERR_NOT_CONVERGED;
   for (int j = 0; j < maxit; ++j) {
     if (j + 1 > c->gm_cap) {  // grow: keep v_0..v_j and z_0..z_{j-1}
-      const int want = 2 * c->gm_cap < maxit ? 2 * c->gm_cap : maxit;
+      int want = 2 * c->gm_cap < maxit ? 2 * c->gm_cap : maxit;
+      size_t freeb = 0, totalb = 0;
+      HIPCHK(c, hipMemGetInfo(&freeb, &totalb));
+      // the new basis is allocated while the old one is still held
+      const double fit = (0.9 * (double)freeb / (8.0 * (double)n) - 1.0) / 2.0;
+      if (fit < want) want = (int)fit;
+      if (want <= c->gm_cap)
+        return fail(c, DGMG_ERR_ALLOC, "GMRES basis does not fit in device memory");
       RET(ensure_gmres(c, want, j + 1, j));
       bind();
     }
@@ -1108,14 +1120,18 @@ DGMG_API dgmg_status dgmg_patch_eigen(int degree, double sigma, int smoother_var
   if (degree < 1 || degree > dgmg::kMaxDegree || !(sigma > 0) || type < 0 || type > 3 || !S || !lam)
     return DGMG_ERR_ARG;
   if (smoother_variant != DGMG_SMOOTH_EXACT && smoother_variant != DGMG_SMOOTH_LOCAL &&
-      smoother_variant != DGMG_SMOOTH_FULL)
+      smoother_variant != DGMG_SMOOTH_FULL && smoother_variant != DGMG_SMOOTH_CLAMPED)
     return DGMG_ERR_ARG;
+  if (smoother_variant == DGMG_SMOOTH_CLAMPED && degree < 3) return DGMG_ERR_ARG;
   dgmg::HostTables H;
   const char* err = nullptr;
   if (!dgmg::build_host_tables(degree, sigma, H, &err)) return DGMG_ERR_ARG;
-  const bool full = smoother_variant == DGMG_SMOOTH_FULL;
-  std::memcpy(S, (full ? H.Sf : H.S)[type].data(), sizeof(double) * H.E * H.E);
-  std::memcpy(lam, (full ? H.lamf : H.lam)[type].data(), sizeof(double) * H.E);
+  const std::vector<double>* Ss = H.S;
+  const std::vector<double>* Ls = H.lam;
+  if (smoother_variant == DGMG_SMOOTH_FULL) { Ss = H.Sf; Ls = H.lamf; }
+  if (smoother_variant == DGMG_SMOOTH_CLAMPED) { Ss = H.Sc; Ls = H.lamc; }
+  std::memcpy(S, Ss[type].data(), sizeof(double) * H.E * H.E);
+  std::memcpy(lam, Ls[type].data(), sizeof(double) * H.E);
   return DGMG_OK;
 }
 

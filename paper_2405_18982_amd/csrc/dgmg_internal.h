@@ -22,6 +22,7 @@ constexpr int kSmoothShapes = 4;  // workgroup shapes x prefetch of b for smooth
 //         Dirichlet local space, padded to E (unused eigenvalue slots hold a
 //         huge finite value)
 //   Sf[t], lamf[t] : the same on the whole patch (Full kernel)
+//   Sc[t], lamc[t] : C S on the clamped space with basis C (clamped kernel)
 //   P   : stacked prolongation, P[(o n + mu) n + nu] = phi_nu((xi_mu + o)/2)
 template <int K, typename T>
 struct Tab {
@@ -36,6 +37,8 @@ struct Tab {
   T lam[4][E];
   T Sf[4][E * E];
   T lamf[4][E];
+  T Sc[4][E * E];
+  T lamc[4][E];
   T P[E * n];
 };
 

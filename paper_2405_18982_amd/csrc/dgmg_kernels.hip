@@ -116,6 +116,10 @@ template <typename T>
 struct Sides {
   bool bl, br;   // left / right outer face on the domain boundary (Nitsche)
   T aL, bL, aR, bR;  // interior-neighbour couplings (ignored on boundary sides)
+  // the paper's Dirichlet residual: on interior outer faces leave out the
+  // consistency term -[[u]].{grad v} altogether (its inside half, carried by
+  // the cell block, is cancelled from the line's own end value)
+  bool lit;
 };
 
 // o (+)= 1-D SIPG of the patch line v
@@ -157,6 +161,8 @@ __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const
     aR = -half * g1;
     bR = -half * v.v[E - 1];
   }
+  if (!sd.bl && sd.lit) bL = -half * v.v[0];
+  if (!sd.br && sd.lit) bR = half * v.v[E - 1];
   const T bLc = half * tR;   // beta seen by the left cell from its right neighbour
   const T bRc = -half * tL;  // beta seen by the right cell from its left neighbour
   o.v[0] += aL;
@@ -170,29 +176,38 @@ __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const
   }
 }
 
-// Fast-diagonalisation contractions for patch type TY (padded S: rows p in
-// [PLO, PHI) and columns q < QN are the only non-zeros).  FULL selects the
-// whole-patch eigenpairs of the Full kernel (no padding).
-template <int TY> struct FDB;
-template <> struct FDB<0> { static constexpr int PLO = 1, PHI = E - 1, QN = E - 2; };
-template <> struct FDB<1> { static constexpr int PLO = 0, PHI = E - 1, QN = E - 1; };
-template <> struct FDB<2> { static constexpr int PLO = 1, PHI = E, QN = E - 1; };
-template <> struct FDB<3> { static constexpr int PLO = 0, PHI = E, QN = E; };
+// Fast-diagonalisation contractions for patch type TY of a local space SP:
+// SP_DIR the Dirichlet space, SP_FULL the whole patch, SP_CLAMPED the clamped
+// space (tables C S).  Padded S: rows p in [PLO, PHI) and columns q < QN are
+// the only non-zeros.
+constexpr int SP_DIR = 0, SP_FULL = 1, SP_CLAMPED = 2;
+template <int SP, int TY> struct FDB;
+template <> struct FDB<SP_DIR, 0> { static constexpr int PLO = 1, PHI = E - 1, QN = E - 2; };
+template <> struct FDB<SP_DIR, 1> { static constexpr int PLO = 0, PHI = E - 1, QN = E - 1; };
+template <> struct FDB<SP_DIR, 2> { static constexpr int PLO = 1, PHI = E, QN = E - 1; };
+template <> struct FDB<SP_DIR, 3> { static constexpr int PLO = 0, PHI = E, QN = E; };
+template <int TY> struct FDB<SP_FULL, TY> { static constexpr int PLO = 0, PHI = E, QN = E; };
+// clamped: value and derivative fixed at each interior-face end (two
+// unknowns fewer per clamped end; the end node itself stays zero)
+template <> struct FDB<SP_CLAMPED, 0> { static constexpr int PLO = 1, PHI = E - 1, QN = E - 4; };
+template <> struct FDB<SP_CLAMPED, 1> { static constexpr int PLO = 0, PHI = E - 1, QN = E - 2; };
+template <> struct FDB<SP_CLAMPED, 2> { static constexpr int PLO = 1, PHI = E, QN = E - 2; };
+template <> struct FDB<SP_CLAMPED, 3> { static constexpr int PLO = 0, PHI = E, QN = E; };
 
-template <typename T, bool FULL>
+template <typename T, int SP>
 __device__ __forceinline__ const T* fd_S(const Tab<K, T>* __restrict__ t, int ty) {
-  return FULL ? t->Sf[ty] : t->S[ty];
+  return SP == SP_FULL ? t->Sf[ty] : SP == SP_CLAMPED ? t->Sc[ty] : t->S[ty];
 }
-template <typename T, bool FULL>
+template <typename T, int SP>
 __device__ __forceinline__ const T* fd_lam(const Tab<K, T>* __restrict__ t, int ty) {
-  return FULL ? t->lamf[ty] : t->lam[ty];
+  return SP == SP_FULL ? t->lamf[ty] : SP == SP_CLAMPED ? t->lamc[ty] : t->lam[ty];
 }
 
 // o[q] = sum_p S[p][q] v[p]
-template <typename T, int TY, bool FULL>
+template <typename T, int TY, int SP>
 __device__ __forceinline__ void line_St_t(const Tab<K, T>* __restrict__ t, const Line<T>& v, Line<T>& o) {
-  using B = FDB<FULL ? 3 : TY>;
-  const T* S = fd_S<T, FULL>(t, TY);
+  using B = FDB<SP, TY>;
+  const T* S = fd_S<T, SP>(t, TY);
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     T s = T(0);
@@ -204,10 +219,10 @@ __device__ __forceinline__ void line_St_t(const Tab<K, T>* __restrict__ t, const
   }
 }
 // o[p] = sum_q S[p][q] v[q]
-template <typename T, int TY, bool FULL>
+template <typename T, int TY, int SP>
 __device__ __forceinline__ void line_S_t(const Tab<K, T>* __restrict__ t, const Line<T>& v, Line<T>& o) {
-  using B = FDB<FULL ? 3 : TY>;
-  const T* S = fd_S<T, FULL>(t, TY);
+  using B = FDB<SP, TY>;
+  const T* S = fd_S<T, SP>(t, TY);
 #pragma unroll
   for (int p = 0; p < E; ++p) {
     T s = T(0);
@@ -218,22 +233,22 @@ __device__ __forceinline__ void line_S_t(const Tab<K, T>* __restrict__ t, const 
     o.v[p] = s;
   }
 }
-template <typename T, bool FULL>
+template <typename T, int SP>
 __device__ __forceinline__ void line_St(const Tab<K, T>* __restrict__ t, int ty, const Line<T>& v, Line<T>& o) {
   switch (ty) {
-    case 0: line_St_t<T, 0, FULL>(t, v, o); break;
-    case 1: line_St_t<T, 1, FULL>(t, v, o); break;
-    case 2: line_St_t<T, 2, FULL>(t, v, o); break;
-    default: line_St_t<T, 3, FULL>(t, v, o); break;
+    case 0: line_St_t<T, 0, SP>(t, v, o); break;
+    case 1: line_St_t<T, 1, SP>(t, v, o); break;
+    case 2: line_St_t<T, 2, SP>(t, v, o); break;
+    default: line_St_t<T, 3, SP>(t, v, o); break;
   }
 }
-template <typename T, bool FULL>
+template <typename T, int SP>
 __device__ __forceinline__ void line_S(const Tab<K, T>* __restrict__ t, int ty, const Line<T>& v, Line<T>& o) {
   switch (ty) {
-    case 0: line_S_t<T, 0, FULL>(t, v, o); break;
-    case 1: line_S_t<T, 1, FULL>(t, v, o); break;
-    case 2: line_S_t<T, 2, FULL>(t, v, o); break;
-    default: line_S_t<T, 3, FULL>(t, v, o); break;
+    case 0: line_S_t<T, 0, SP>(t, v, o); break;
+    case 1: line_S_t<T, 1, SP>(t, v, o); break;
+    case 2: line_S_t<T, 2, SP>(t, v, o); break;
+    default: line_S_t<T, 3, SP>(t, v, o); break;
   }
 }
 
@@ -292,8 +307,8 @@ __device__ __forceinline__ long long xrow_offset(int N, const PatchPos& P, int p
 
 // Side flags and x-face couplings of x-line (py, pz), read from the rows of
 // the outside neighbours.  MODE 0: full operator rows; 1: smoother (only the
-// traces matter, alpha acts on dropped rows); 2: paper-literal smoother
-// (interior neighbours ignored).
+// traces matter, alpha acts on dropped rows); 2: the paper's Dirichlet
+// residual (interior neighbours ignored, consistency term left out).
 template <typename T, int MODE>
 __device__ __forceinline__ Sides<T> xline_sides(const Tab<K, T>* __restrict__ t, const T* __restrict__ x,
                                                 int N, const PatchPos& P, long long row0) {
@@ -303,6 +318,7 @@ __device__ __forceinline__ Sides<T> xline_sides(const Tab<K, T>* __restrict__ t,
   sd.bl = (P.lo[0] == 0);
   sd.br = (P.lo[0] + 1 == N - 1);
   sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  sd.lit = (MODE == 2);
   if (MODE != 2) {
     if (!sd.bl) {
       const T* r = x + row0 - NC;
@@ -333,7 +349,7 @@ __device__ __forceinline__ Sides<T> xline_sides(const Tab<K, T>* __restrict__ t,
 // Raw face data of interior neighbours across y- (and z-) faces.  Entry i
 // enumerates (dir, side, face node f); f = a + E b with (a, b) the tangential
 // patch coordinates in increasing direction order.  NCOMP = 2 stores
-// (alpha, beta), NCOMP = 1 stores beta only.  Layout: ext[(fd * 2 + side) *
+// (alpha, beta), NCOMP = 1 stores beta only (MODE 2 stores zeros).  Layout: ext[(fd * 2 + side) *
 // NCOMP + comp][f] with fd = dir - 1.
 template <typename T, int MODE>
 __device__ __forceinline__ void gather_ext(const Tab<K, T>* __restrict__ t, const T* __restrict__ x,
@@ -406,6 +422,7 @@ __device__ __forceinline__ Sides<T> yline_sides(const Tab<K, T>* __restrict__ t,
   sd.bl = (P.lo[1] == 0);
   sd.br = (P.lo[1] + 1 == N - 1);
   sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  sd.lit = false;
   if (NCOMP == 2) {
     if (!sd.bl) { sd.aL = ext_mx<T>(t, ext + 0 * NF, px, pz); sd.bL = ext_mx<T>(t, ext + 1 * NF, px, pz); }
     if (!sd.br) { sd.aR = ext_mx<T>(t, ext + 2 * NF, px, pz); sd.bR = ext_mx<T>(t, ext + 3 * NF, px, pz); }
@@ -419,7 +436,7 @@ __device__ __forceinline__ Sides<T> yline_sides(const Tab<K, T>* __restrict__ t,
 // Sides of the smoother's y-line (px, pz): the traces of the y-neighbours at
 // nodes (a, k or 0, pz), a in the cell block of px, contracted with M_x
 // straight from global memory (n contiguous values per side).  MODE 2 (the
-// paper-literal kernel) ignores interior neighbours.
+// paper's Dirichlet residual) ignores interior neighbours.
 template <typename T, int MODE>
 __device__ __forceinline__ Sides<T> yline_sides_global(const Tab<K, T>* __restrict__ t,
                                                        const T* __restrict__ x, int N,
@@ -428,6 +445,7 @@ __device__ __forceinline__ Sides<T> yline_sides_global(const Tab<K, T>* __restri
   sd.bl = (P.lo[1] == 0);
   sd.br = (P.lo[1] + 1 == N - 1);
   sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  sd.lit = (MODE == 2);
   if (MODE == 2) return sd;
   const int mu = px % n;
   const int cx = P.lo[0] + px / n;
@@ -477,6 +495,7 @@ __device__ __forceinline__ Sides<T> zline_sides(const Tab<K, T>* __restrict__ t,
   sd.bl = (P.lo[2] == 0);
   sd.br = (P.lo[2] + 1 == N - 1);
   sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  sd.lit = false;
   const T* z = ext + extz_base<NCOMP>();
   if (NCOMP == 2) {
     if (!sd.bl) { sd.aL = ext_my<T>(t, z + 0 * NF, px, py); sd.bL = ext_my<T>(t, z + 1 * NF, px, py); }
@@ -558,7 +577,8 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
         Line<T> c, d, y;
         load_line(B, base, stride, c);
         load_line(A, base, stride, d);
-        const Sides<T> sd = zline_sides<T, NCOMP>(t, ext, N, P, px, py);
+        Sides<T> sd = zline_sides<T, NCOMP>(t, ext, N, P, px, py);
+        sd.lit = (MODE == 2);
         line_mass<T>(t, c, y);
         line_sipg<T, true>(t, d, sd, y);
         emit(i, base, stride, y);
@@ -703,18 +723,23 @@ k_mass(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restric
 // One colour of Alg. 1: local residual on the patch, then fast
 // diagonalisation x|V_j += (x)S (sum lambda)^{-1} (x)S^T r_j.
 //   MODE 1: Dirichlet kernel, consistent residual (b - A x)|V_j, in place;
-//   MODE 2: Dirichlet kernel, paper-literal residual (patch cells only), in place;
+//   MODE 2: Dirichlet kernel, the paper's residual: patch cells only, the
+//           consistency term left out on interior outer faces; in place;
 //   MODE 3: Full kernel: V_j = the whole patch, r = (b - A x)|patch with x taken
 //           from xin, result written to xout.  Same-colour patches read each
 //           other's cells (face neighbours), so the colour reads one copy of x
 //           and writes the other; the launch also carries the partial patches
 //           at the mesh boundary, which copy their in-domain cells unchanged.
+//   MODE 4: clamped kernel: the residual from the patch cells alone (the
+//           terms it misses act on directions the clamped space annihilates),
+//           the FD solve on the clamped space; in place.
 template <typename T, int PPB, int MODE, bool PREFETCH>
 __global__ void __launch_bounds__(TPP * PPB)
 k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
          const T* __restrict__ xin, T* __restrict__ xout, const T* __restrict__ b, long long ndof) {
   constexpr bool FULL = (MODE == 3);
-  constexpr int OPM = FULL ? 0 : MODE;  // operator-pass mode (side data)
+  constexpr int SP = FULL ? SP_FULL : (MODE == 4) ? SP_CLAMPED : SP_DIR;
+  constexpr int OPM = FULL ? 0 : (MODE == 4) ? 2 : MODE;  // operator-pass mode (side data)
   // operator face data (full rows) for the Full kernel, z-face traces only
   // for the Dirichlet kernels
   constexpr int PP = FULL ? Smem<2, (D - 1) * 2 * 2 * NF>::per_patch
@@ -772,7 +797,7 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
                             else read_lastline<T>(br, g.N, P, l, r);
 #pragma unroll
                             for (int p = 0; p < E; ++p) r.v[p] -= scale * v.v[p];
-                            line_St<T, FULL>(t, (D == 3) ? tyz : tyy, r, o);
+                            line_St<T, SP>(t, (D == 3) ? tyz : tyy, r, o);
                             store_line(A, base, stride, o);
                           });
   __syncthreads();
@@ -784,7 +809,7 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
         line_geom(0, i, base, stride);
         Line<T> v, o;
         load_line(A, base, stride, v);
-        line_St<T, FULL>(t, tyx, v, o);
+        line_St<T, SP>(t, tyx, v, o);
         store_line(A, base, stride, o);
       }
     __syncthreads();
@@ -794,14 +819,14 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
         const int qx = i % E, qz = i / E;
         int base, stride;
         line_geom(1, i, base, stride);
-        const T* ly = fd_lam<T, FULL>(t, tyy);
-        const T lt = fd_lam<T, FULL>(t, tyx)[qx] + fd_lam<T, FULL>(t, tyz)[qz];
+        const T* ly = fd_lam<T, SP>(t, tyy);
+        const T lt = fd_lam<T, SP>(t, tyx)[qx] + fd_lam<T, SP>(t, tyz)[qz];
         Line<T> v, o;
         load_line(A, base, stride, v);
-        line_St<T, FULL>(t, tyy, v, o);
+        line_St<T, SP>(t, tyy, v, o);
 #pragma unroll
         for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(ly[q] + lt));
-        line_S<T, FULL>(t, tyy, o, v);
+        line_S<T, SP>(t, tyy, o, v);
         store_line(A, base, stride, v);
       }
     __syncthreads();
@@ -812,7 +837,7 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
         line_geom(2, i, base, stride);
         Line<T> v, o;
         load_line(A, base, stride, v);
-        line_S<T, FULL>(t, tyz, v, o);
+        line_S<T, SP>(t, tyz, v, o);
         store_line(A, base, stride, o);
       }
     __syncthreads();
@@ -823,14 +848,14 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
         const int qy = i;
         int base, stride;
         line_geom(0, i, base, stride);
-        const T* lx = fd_lam<T, FULL>(t, tyx);
-        const T lt = fd_lam<T, FULL>(t, tyy)[qy];
+        const T* lx = fd_lam<T, SP>(t, tyx);
+        const T lt = fd_lam<T, SP>(t, tyy)[qy];
         Line<T> v, o;
         load_line(A, base, stride, v);
-        line_St<T, FULL>(t, tyx, v, o);
+        line_St<T, SP>(t, tyx, v, o);
 #pragma unroll
         for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(lx[q] + lt));
-        line_S<T, FULL>(t, tyx, o, v);
+        line_S<T, SP>(t, tyx, o, v);
         store_line(A, base, stride, v);
       }
     __syncthreads();
@@ -841,7 +866,7 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
         line_geom(1, i, base, stride);
         Line<T> v, o;
         load_line(A, base, stride, v);
-        line_S<T, FULL>(t, tyy, v, o);
+        line_S<T, SP>(t, tyy, v, o);
         store_line(A, base, stride, o);
       }
     __syncthreads();
@@ -861,7 +886,7 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
       load_line(A, base, stride, dl);
       if constexpr (D == 3) {
         Line<T> o;
-        line_S<T, FULL>(t, tyx, dl, o);
+        line_S<T, SP>(t, tyx, dl, o);
         dl = o;
       }
       // whole rows: the dropped end nodes of a Dirichlet V_j are rewritten
@@ -1044,7 +1069,7 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
     line_geom(0, i, base, stride);
     Line<T> v, o;
     read_xline<T>(b + roff, xrow_offset(2, P, py, pz), v);
-    line_St_t<T, 3, false>(t, v, o);
+    line_St_t<T, 3, SP_DIR>(t, v, o);
     store_line(tile, base, stride, o);
   }
   __syncthreads();
@@ -1056,14 +1081,14 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
       line_geom(dir, i, base, stride);
       Line<T> v, o;
       load_line(tile, base, stride, v);
-      line_St_t<T, 3, false>(t, v, o);
+      line_St_t<T, 3, SP_DIR>(t, v, o);
       if (dir == D - 1) {
         const int qa = i % E, qb = i / E;
         T lt = t->lam[3][qa];
         if (D == 3) lt += t->lam[3][qb];
 #pragma unroll
         for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(t->lam[3][q] + lt));
-        line_S_t<T, 3, false>(t, o, v);
+        line_S_t<T, 3, SP_DIR>(t, o, v);
         o = v;
       }
       store_line(tile, base, stride, o);
@@ -1078,7 +1103,7 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
       line_geom(dir, i, base, stride);
       Line<T> v, o;
       load_line(tile, base, stride, v);
-      line_S_t<T, 3, false>(t, v, o);
+      line_S_t<T, 3, SP_DIR>(t, v, o);
       store_line(tile, base, stride, o);
     }
     __syncthreads();
@@ -1089,7 +1114,7 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
     line_geom(0, i, base, stride);
     Line<T> v, o;
     load_line(tile, base, stride, v);
-    line_S_t<T, 3, false>(t, v, o);
+    line_S_t<T, 3, SP_DIR>(t, v, o);
     const long long row0 = roff + xrow_offset(2, P, py, pz);
 #pragma unroll
     for (int a = 0; a < n; ++a) {
@@ -1128,7 +1153,8 @@ hipError_t launch_mass(const void* tab, PatchGrid g, T scale, const T* x, T* y, 
   return hipGetLastError();
 }
 // smoother shapes: bit 0 selects the workgroup shape, bit 1 the prefetch of b;
-// variant 0 / 1 / 2: Dirichlet consistent / Dirichlet paper-literal / Full
+// variant 0 / 1 / 2 / 3: Dirichlet consistent / Dirichlet with the paper's
+// residual / Full / clamped
 template <typename T, int V>
 hipError_t launch_smooth(const void* tab, PatchGrid g, T scale, T inv_scale, int variant,
                          const T* xin, T* xout, const T* b, int nrhs, long long ndof, hipStream_t s) {
@@ -1139,6 +1165,9 @@ hipError_t launch_smooth(const void* tab, PatchGrid g, T scale, T inv_scale, int
   if (variant == 2)
     hipLaunchKernelGGL((k_smooth<T, PPB, 3, PF>), grid, dim3(TPP * PPB), 0, s, tb, g, scale,
                        inv_scale, xin, xout, b, ndof);
+  else if (variant == 3)
+    hipLaunchKernelGGL((k_smooth<T, PPB, 4, PF>), grid, dim3(TPP * PPB), 0, s, tb, g, scale,
+                       inv_scale, xout, xout, b, ndof);
   else if (variant == 1)
     hipLaunchKernelGGL((k_smooth<T, PPB, 2, PF>), grid, dim3(TPP * PPB), 0, s, tb, g, scale,
                        inv_scale, xout, xout, b, ndof);

@@ -2,8 +2,9 @@
 // multigrid (Sec. 2.2, Sec. 3.2, Appendix A): Gauss-Lobatto nodes, Lagrange
 // basis, cell mass/stiffness, the 1-D SIPG cell block, the embedding
 // prolongation, and the fast-diagonalisation eigenpairs L S = M S Lambda of
-// the two-cell patch restricted to the Dirichlet local space and on the whole
-// patch (Full kernel), for each of the four 1-D patch types.  Everything is computed at h = 1, kappa = 1; the
+// the two-cell patch restricted to the Dirichlet local space, on the whole
+// patch (Full kernel) and on the clamped space, for each of the four 1-D
+// patch types.  Everything is computed at h = 1, kappa = 1; the
 // kernels scale by kappa h^(d-2).
 #include "dgmg_setup.h"
 
@@ -130,19 +131,27 @@ void jacobi_eigen(std::vector<double> A, int m, std::vector<double>& w, std::vec
   for (int i = 0; i < m; ++i) w[i] = A[i * m + i];
 }
 
-// Generalised eigenpairs L S = M S Lambda of the E x E patch matrices L, M
-// restricted to the node set keep, padded back to E: S[p*E + q] (zero rows
-// for dropped nodes, zero columns q >= |keep|), lam[q] (+inf unused).
-// Via M = C C^T: C^{-1} L C^{-T} = Q Lambda Q^T, S = C^{-T} Q (S^T M S = I).
-bool patch_eigenpairs(const std::vector<double>& L, const std::vector<double>& Mp, int E,
-                      const std::vector<int>& keep, std::vector<double>& Sout,
+// Generalised eigenpairs of the E x E patch matrices L, M on the subspace
+// spanned by the m columns of Cb (row-major E x m): L_C S = M_C S Lambda with
+// L_C = Cb^T L Cb, M_C = Cb^T M Cb, returned as Cb S padded to E x E
+// (Sout[p*E + q], zero columns q >= m) and lam (+inf in unused slots).
+// Via M_C = C C^T: C^{-1} L_C C^{-T} = Q Lambda Q^T, S = C^{-T} Q (S^T M_C S = I).
+bool basis_eigenpairs(const std::vector<double>& L, const std::vector<double>& Mp, int E,
+                      const std::vector<double>& Cb, int m, std::vector<double>& Sout,
                       std::vector<double>& lamout, const char** err) {
-  const int m = (int)keep.size();
-  std::vector<double> Lt(m * m), Mt(m * m);
+  std::vector<double> Lt(m * m, 0.0), Mt(m * m, 0.0);
   for (int i = 0; i < m; ++i)
     for (int j = 0; j < m; ++j) {
-      Lt[i * m + j] = L[keep[i] * E + keep[j]];
-      Mt[i * m + j] = Mp[keep[i] * E + keep[j]];
+      double sl = 0.0, sm = 0.0;
+      for (int p = 0; p < E; ++p)
+        for (int q = 0; q < E; ++q) {
+          const double w = Cb[p * m + i] * Cb[q * m + j];
+          if (w == 0.0) continue;
+          sl += w * L[p * E + q];
+          sm += w * Mp[p * E + q];
+        }
+      Lt[i * m + j] = sl;
+      Mt[i * m + j] = sm;
     }
   std::vector<double> C;
   if (!cholesky(Mt, m, C)) { *err = "patch mass matrix is not positive definite"; return false; }
@@ -179,9 +188,54 @@ bool patch_eigenpairs(const std::vector<double>& L, const std::vector<double>& M
   lamout.assign(E, std::numeric_limits<double>::infinity());
   for (int q = 0; q < m; ++q) {
     lamout[q] = w[q];
-    for (int i = 0; i < m; ++i) Sout[keep[i] * E + q] = S[i * m + q];
+    for (int p = 0; p < E; ++p) {
+      double s = 0.0;
+      for (int i = 0; i < m; ++i) s += Cb[p * m + i] * S[i * m + q];
+      Sout[p * E + q] = s;
+    }
   }
   return true;
+}
+
+// The same on the coordinate subspace of the nodes in keep.
+bool patch_eigenpairs(const std::vector<double>& L, const std::vector<double>& Mp, int E,
+                      const std::vector<int>& keep, std::vector<double>& Sout,
+                      std::vector<double>& lamout, const char** err) {
+  const int m = (int)keep.size();
+  std::vector<double> Cb(E * m, 0.0);
+  for (int i = 0; i < m; ++i) Cb[keep[i] * m + i] = 1.0;
+  return basis_eigenpairs(L, Mp, E, Cb, m, Sout, lamout, err);
+}
+
+// Basis (row-major E x m) of the clamped space of a 1-D patch type: value and
+// derivative vanish at every end on an interior face.  With Gauss-Lobatto
+// nodes the value at an end is the end node; the derivative condition fixes
+// the neighbouring node: left end v_1 = -sum_{a>=2} d0_a v_a / d0_1, right end
+// v_{k-1} = -sum_{a<=k-2} d1_a v_a / d1_{k-1} (right cell).  Needs k >= 2.
+std::vector<double> clamped_basis(int k, int t, const std::vector<double>& d0,
+                                  const std::vector<double>& d1, int& m) {
+  const int n = k + 1, E = 2 * n;
+  const bool cl = !(t & 1), cr = !(t & 2);
+  std::vector<std::vector<double>> cols;
+  for (int a = 0; a < n; ++a) {  // left cell
+    if (cl && a < 2) continue;
+    std::vector<double> c(E, 0.0);
+    c[a] = 1.0;
+    if (cl) c[1] = -d0[a] / d0[1];
+    cols.push_back(c);
+  }
+  for (int a = 0; a < n; ++a) {  // right cell
+    if (cr && a > k - 2) continue;
+    std::vector<double> c(E, 0.0);
+    c[n + a] = 1.0;
+    if (cr) c[n + k - 1] = -d1[a] / d1[k - 1];
+    cols.push_back(c);
+  }
+  m = (int)cols.size();
+  std::vector<double> Cb(E * m);
+  for (int p = 0; p < E; ++p)
+    for (int i = 0; i < m; ++i) Cb[p * m + i] = cols[i][p];
+  return Cb;
 }
 
 }  // namespace
@@ -288,6 +342,15 @@ bool build_host_tables(int k, double sigma, HostTables& T, const char** err) {
     std::vector<int> all(E);
     for (int p = 0; p < E; ++p) all[p] = p;
     if (!patch_eigenpairs(L, Mp, E, all, T.Sf[t], T.lamf[t], err)) return false;
+    // clamped kernel (k >= 2; the library uses it for k >= 3)
+    if (k >= 2) {
+      int m = 0;
+      const std::vector<double> Cb = clamped_basis(k, t, T.d0, T.d1, m);
+      if (!basis_eigenpairs(L, Mp, E, Cb, m, T.Sc[t], T.lamc[t], err)) return false;
+    } else {
+      T.Sc[t].assign(E * E, 0.0);
+      T.lamc[t].assign(E, std::numeric_limits<double>::infinity());
+    }
   }
   return true;
 }

@@ -21,6 +21,9 @@ struct HostTables {
   // the same on the whole two-cell patch (Full kernel; every slot used)
   std::vector<double> Sf[4];
   std::vector<double> lamf[4];
+  // clamped space (basis C): C S padded to E x E, eigenvalues (+inf unused)
+  std::vector<double> Sc[4];
+  std::vector<double> lamc[4];
 };
 
 // Builds every table; returns false (with a message) if a factorisation fails,

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgmg.so")
 
 FP64, FP32 = 64, 32
-SMOOTH_EXACT, SMOOTH_LOCAL, SMOOTH_FULL = 0, 1, 2
+SMOOTH_EXACT, SMOOTH_LOCAL, SMOOTH_FULL, SMOOTH_CLAMPED = 0, 1, 2, 3
 
 STATUS = {
     0: "DGMG_OK", -1: "DGMG_ERR_ARG", -2: "DGMG_ERR_ALLOC", -3: "DGMG_ERR_HIP",

@@ -1,12 +1,12 @@
 """Fractional iteration counts of the multigrid-preconditioned GMRES on the GPU
 (Sec. 3.3, Tables 1 and 2): 3-D, f = 1, relative accuracy 1e-8, penalty
 sigma = 2k(k+1), one V-cycle with one pre- and one post-smoothing step per
-level, for the Full and Dirichlet vertex-patch kernels (consistent and
-paper-literal residual) over degrees and levels.
+level, for the Full, Dirichlet (consistent residual and the paper's) and
+clamped vertex-patch kernels over degrees and levels.
 
 nu = -8 / log10(rbar), rbar = (|r_n| / |r_0|)^(1/n) over the n GMRES steps.
 
-    python -m paper_2405_18982_amd.nu_tables [--kernels full,exact,local]
+    python -m paper_2405_18982_amd.nu_tables [--kernels full,exact,local,clamped]
         [--degrees 3,4,5,6,7] [--levels 2,3,4,5] [--precision 64] [--json out.jsonl]
 
 Prints one table per kernel (rows L, columns Q_k) and, with --json, one JSON
@@ -18,7 +18,8 @@ import math
 import time
 
 KERNELS = {"full": "Full kernel", "exact": "Dirichlet kernel, consistent residual",
-           "local": "Dirichlet kernel, paper-literal residual"}
+           "local": "Dirichlet kernel, the paper's residual (outer-face consistency term left out)",
+           "clamped": "clamped kernel"}
 
 
 def nu_of(hist):
@@ -33,7 +34,8 @@ def run(kernel, k, L, precision=64, rtol=1e-8, maxit=200):
     import torch
 
     from paper_2405_18982_amd import dgmg
-    variant = {"full": dgmg.SMOOTH_FULL, "exact": dgmg.SMOOTH_EXACT, "local": dgmg.SMOOTH_LOCAL}[kernel]
+    variant = {"full": dgmg.SMOOTH_FULL, "exact": dgmg.SMOOTH_EXACT, "local": dgmg.SMOOTH_LOCAL,
+               "clamped": dgmg.SMOOTH_CLAMPED}[kernel]
     prob = dgmg.Problem(3, k, L, sigma=2.0 * k * (k + 1), precision=precision, variant=variant)
     try:
         ones = torch.ones(prob.ndofs(), dtype=torch.float64, device="cuda")
@@ -41,7 +43,16 @@ def run(kernel, k, L, precision=64, rtol=1e-8, maxit=200):
         del ones
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, m, hist = prob.gmres(b, rtol=rtol, maxit=maxit, raise_on_nonconvergence=False)
+        try:
+            x, m, hist = prob.gmres(b, rtol=rtol, maxit=maxit, raise_on_nonconvergence=False)
+        except dgmg.DGMGError as e:
+            if e.status != -2:
+                raise
+            # the Krylov basis outgrew device memory (the paper's "---")
+            return {"kernel": kernel, "k": k, "L": L, "ndofs": prob.ndofs(),
+                    "precision": precision, "steps": None, "final_relres": None,
+                    "nu": float("nan"), "seconds": None, "converged": False,
+                    "note": "GMRES basis exceeds device memory"}
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         return {"kernel": kernel, "k": k, "L": L, "ndofs": prob.ndofs(), "precision": precision,
@@ -54,7 +65,7 @@ def run(kernel, k, L, precision=64, rtol=1e-8, maxit=200):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernels", default="full,exact,local")
+    ap.add_argument("--kernels", default="full,exact,local,clamped")
     ap.add_argument("--degrees", default="3,4,5,6,7")
     ap.add_argument("--levels", default="2,3,4,5")
     ap.add_argument("--precision", type=int, default=64, choices=(64, 32))
@@ -70,15 +81,20 @@ def main():
             for k in degrees:
                 r = run(kern, k, L, args.precision)
                 res[(L, k)] = r
-                print(f"{kern} L={L} Q{k}: {r['steps']} steps, nu = {r['nu']:.2f}, "
-                      f"{r['ndofs']} DoFs, {r['seconds']:.2f} s", flush=True)
+                if r["steps"] is None:
+                    print(f"{kern} L={L} Q{k}: {r['note']}", flush=True)
+                else:
+                    print(f"{kern} L={L} Q{k}: {r['steps']} steps, nu = {r['nu']:.2f}, "
+                          f"{r['ndofs']} DoFs, {r['seconds']:.2f} s", flush=True)
                 if out:
                     out.write(json.dumps(r) + "\n")
                     out.flush()
         print(f"\nnu, {KERNELS[kern]} (GMRES 1e-8, f = 1, 3-D, FP{args.precision} V-cycle)")
         print("L  | " + " ".join(f"Q{k:<5d}" for k in degrees))
         for L in levels:
-            print(f"{L:<2d} | " + " ".join(f"{res[(L, k)]['nu']:<6.2f}" for k in degrees))
+            print(f"{L:<2d} | " + " ".join(
+                (f"{res[(L, k)]['nu']:<6.2f}" if res[(L, k)]["steps"] is not None else "---   ")
+                for k in degrees))
         print(flush=True)
     if out:
         out.close()

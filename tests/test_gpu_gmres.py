@@ -19,7 +19,8 @@ if not torch.cuda.is_available():
 
 from paper_2405_18982_amd import dgmg  # noqa: E402
 
-VARIANTS = {"exact": dgmg.SMOOTH_EXACT, "local": dgmg.SMOOTH_LOCAL, "full": dgmg.SMOOTH_FULL}
+VARIANTS = {"exact": dgmg.SMOOTH_EXACT, "local": dgmg.SMOOTH_LOCAL, "full": dgmg.SMOOTH_FULL,
+            "clamped": dgmg.SMOOTH_CLAMPED}
 
 
 def note(msg):
@@ -31,19 +32,21 @@ def one(X):
     return np.ones(X.shape[0])
 
 
-@pytest.mark.parametrize("variant", ["exact", "local", "full"])
+@pytest.mark.parametrize("variant", ["exact", "local", "full", "clamped"])
 @pytest.mark.parametrize("dim,k,L", [(2, 2, 2), (2, 5, 3), (3, 3, 2), (3, 4, 1)])
 def test_gmres_history_and_nu_match_oracle(dim, k, L, variant):
+    if variant == "clamped" and k < 3:
+        pytest.skip("the clamped kernel needs k >= 3")
     note(f"gmres d={dim} k={k} L={L} {variant}")
     sigma = 2.0 * k * (k + 1)  # the paper's penalty for the iteration tables
     prob = dgmg.Problem(dim, k, L, sigma=sigma, variant=VARIANTS[variant])
     N = 2 ** (L + 1)
     b = load_vector(dim, k, N, one)
-    x, m, hist = prob.gmres(torch.from_numpy(b).cuda(), rtol=1e-8, maxit=60)
+    x, m, hist = prob.gmres(torch.from_numpy(b).cuda(), rtol=1e-8, maxit=100)
     X = x.cpu().numpy()
     prob.close()
     H = Hierarchy(dim, k, L, sigma, mode=variant)
-    xo, mo, ho = gmres(H.apply[L], H.vcycle, b, rtol=1e-8, maxit=60)
+    xo, mo, ho = gmres(H.apply[L], H.vcycle, b, rtol=1e-8, maxit=100)
     assert m == mo, (m, mo)
     ho = np.array(ho)
     assert np.all(np.abs(hist - ho) <= 1e-9 + 1e-6 * ho), np.c_[hist, ho]

@@ -9,7 +9,7 @@ import re
 import numpy as np
 import pytest
 
-from oracle.patches import kept_1d
+from oracle.patches import clamped_basis_1d, kept_1d
 from oracle.rhs import node_coords as oracle_coords
 from oracle.smoother import PatchFD
 
@@ -109,3 +109,15 @@ def test_patch_eigenpairs_match_oracle(k, sigma_rule):
             assert np.allclose(Sf.T @ Mp @ Sf, np.eye(E), atol=1e-11)
             Lfinv = Sf @ np.diag(1.0 / lamf) @ Sf.T
             assert np.abs(Lfinv @ Lp - np.eye(E)).max() < 1e-10
+            if k >= 3:
+                # clamped space: C (C^T L C)^{-1} C^T does not depend on the
+                # basis C; the oracle's is orthonormal, the library's is not
+                Sc, lamc = dgmg.patch_eigen(k, sigma, t, dgmg.SMOOTH_CLAMPED)
+                Co = clamped_basis_1d(k, t)
+                mc = Co.shape[1]
+                assert np.all(np.isinf(lamc[mc:])) and np.all(Sc[:, mc:] == 0)
+                Scm = Sc[:, :mc]
+                assert np.allclose(Scm.T @ Mp @ Scm, np.eye(mc), atol=1e-10)
+                ref = Co @ np.linalg.solve(Co.T @ Lp @ Co, Co.T)
+                got = Scm @ np.diag(1.0 / lamc[:mc]) @ Scm.T
+                assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
