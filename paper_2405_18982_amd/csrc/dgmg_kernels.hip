@@ -84,17 +84,21 @@ __device__ __forceinline__ void store_line(T* s, int base, int stride, const Lin
   for (int p = 0; p < E; ++p) s[base + p * stride] = L.v[p];
 }
 
-// o = blockdiag(M, M) v
+// o = blockdiag(M, M) v; the end outputs o[0] and o[E-1] only when need0 /
+// needE (wave-uniform): smoothers drop them on interior patch faces
 template <typename T>
-__device__ __forceinline__ void line_mass(const Tab<K, T>* __restrict__ t, const Line<T>& v, Line<T>& o) {
+__device__ __forceinline__ void line_mass(const Tab<K, T>* __restrict__ t, const Line<T>& v, Line<T>& o,
+                                          bool need0 = true, bool needE = true) {
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int mu = 0; mu < n; ++mu) {
+      const int p = c * n + mu;
+      if ((p == 0 && !need0) || (p == E - 1 && !needE)) continue;
       T s = T(0);
 #pragma unroll
       for (int nu = 0; nu < n; ++nu) s += t->M[mu * n + nu] * v.v[c * n + nu];
-      o.v[c * n + mu] = s;
+      o.v[p] = s;
     }
 }
 
@@ -122,20 +126,23 @@ struct Sides {
   bool lit;
 };
 
-// o (+)= 1-D SIPG of the patch line v
+// o (+)= 1-D SIPG of the patch line v; the end outputs only when need0 / needE
 template <typename T, bool ACC>
 __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const Line<T>& v,
-                                          const Sides<T>& sd, Line<T>& o) {
+                                          const Sides<T>& sd, Line<T>& o, bool need0 = true,
+                                          bool needE = true) {
   const T sg = t->sigma;
   const T half = T(0.5);
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int mu = 0; mu < n; ++mu) {
-      T s = ACC ? o.v[c * n + mu] : T(0);
+      const int p = c * n + mu;
+      if ((p == 0 && !need0) || (p == E - 1 && !needE)) continue;
+      T s = ACC ? o.v[p] : T(0);
 #pragma unroll
       for (int nu = 0; nu < n; ++nu) s += t->Lc[mu * n + nu] * v.v[c * n + nu];
-      o.v[c * n + mu] = s;
+      o.v[p] = s;
     }
   // face between the two patch cells
   const T tR = v.v[n];      // trace of the right cell at its x=0 side
@@ -165,14 +172,20 @@ __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const
   if (!sd.br && sd.lit) bR = half * v.v[E - 1];
   const T bLc = half * tR;   // beta seen by the left cell from its right neighbour
   const T bRc = -half * tL;  // beta seen by the right cell from its left neighbour
-  o.v[0] += aL;
+  if (need0) {
+    o.v[0] += aL;
+    o.v[0] += t->d0[0] * bL + t->d1[0] * bLc;
+  }
   o.v[n - 1] += -sg * tR - half * gR;
   o.v[n] += half * gL - sg * tL;
-  o.v[E - 1] += aR;
+  if (needE) {
+    o.v[E - 1] += aR;
+    o.v[E - 1] += t->d0[n - 1] * bRc + t->d1[n - 1] * bR;
+  }
 #pragma unroll
   for (int mu = 0; mu < n; ++mu) {
-    o.v[mu] += t->d0[mu] * bL + t->d1[mu] * bLc;
-    o.v[n + mu] += t->d0[mu] * bRc + t->d1[mu] * bR;
+    if (mu > 0) o.v[mu] += t->d0[mu] * bL + t->d1[mu] * bLc;
+    if (mu < n - 1) o.v[n + mu] += t->d0[mu] * bRc + t->d1[mu] * bR;
   }
 }
 
@@ -527,6 +540,12 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
                                                 int lane, bool active, Line<T>& xl,
                                                 const Sides<T>& ysd_global, Emit emit) {
   constexpr int NCOMP = (MODE == 0) ? 2 : 1;
+  // the smoothers' residual is only used on V_j: along each direction the two
+  // tile ends are skipped unless they lie on the domain boundary (outputs left
+  // at the ends are never read by a used result)
+  const bool n0x = MODE == 0 || (P.ty[0] & 1), nEx = MODE == 0 || (P.ty[0] & 2);
+  const bool n0y = MODE == 0 || (P.ty[1] & 1), nEy = MODE == 0 || (P.ty[1] & 2);
+  const bool n0z = MODE == 0 || (P.ty[2] & 1), nEz = MODE == 0 || (P.ty[2] & 2);
   // X0: a = M_x x -> A, b = L_x x -> B
   if (active) {
     gather_ext<T, MODE>(t, x, N, P, lane, ext);
@@ -538,8 +557,8 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
       int base, stride;
       line_geom(0, i, base, stride);
       Line<T> a, b;
-      line_mass<T>(t, xl, a);
-      line_sipg<T, false>(t, xl, sd, b);
+      line_mass<T>(t, xl, a, n0x, nEx);
+      line_sipg<T, false>(t, xl, sd, b, n0x, nEx);
       store_line(A, base, stride, a);
       store_line(B, base, stride, b);
     }
@@ -557,9 +576,9 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
           load_line(A, base, stride, a);
           load_line(B, base, stride, b);
           const Sides<T> sd = (MODE == 0) ? yline_sides<T, NCOMP>(t, ext, N, P, px, pz) : ysd_global;
-          line_mass<T>(t, b, c);
-          line_sipg<T, true>(t, a, sd, c);
-          line_mass<T>(t, a, d);
+          line_mass<T>(t, b, c, n0y, nEy);
+          line_sipg<T, true>(t, a, sd, c, n0y, nEy);
+          line_mass<T>(t, a, d, n0y, nEy);
           store_line(B, base, stride, c);
           store_line(A, base, stride, d);
         } else {
@@ -579,8 +598,8 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
         load_line(A, base, stride, d);
         Sides<T> sd = zline_sides<T, NCOMP>(t, ext, N, P, px, py);
         sd.lit = (MODE == 2);
-        line_mass<T>(t, c, y);
-        line_sipg<T, true>(t, d, sd, y);
+        line_mass<T>(t, c, y, n0z, nEz);
+        line_sipg<T, true>(t, d, sd, y, n0z, nEz);
         emit(i, base, stride, y);
       }
     }
@@ -595,8 +614,8 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
         load_line(A, base, stride, a);
         load_line(B, base, stride, b);
         const Sides<T> sd = (MODE == 0) ? yline_sides<T, NCOMP>(t, ext, N, P, px, 0) : ysd_global;
-        line_mass<T>(t, b, y);
-        line_sipg<T, true>(t, a, sd, y);
+        line_mass<T>(t, b, y, n0y, nEy);
+        line_sipg<T, true>(t, a, sd, y, n0y, nEy);
         emit(i, base, stride, y);
       }
     }
@@ -756,9 +775,11 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
   const T* xr = (FULL ? xin : xout) + roff;
   const T* br = b + roff;
   const PatchPos P = patch_pos(g, inrange ? pid : 0);
-  bool whole = true;
+  bool whole = true;  // partial patches exist only in the Full kernel's launches
+  if (FULL) {
 #pragma unroll
-  for (int i = 0; i < D; ++i) whole = whole && P.lo[i] >= 0 && P.lo[i] + 1 < g.N;
+    for (int i = 0; i < D; ++i) whole = whole && P.lo[i] >= 0 && P.lo[i] + 1 < g.N;
+  }
   const bool active = inrange && whole;
   if (FULL && inrange && !whole) {
     // partial patch: copy the rows of its in-domain cells
