@@ -298,9 +298,12 @@ dgmg_status ensure_alt(dgmg_ctx* c);
 // One smoothing step.  The Dirichlet kernels update x in place colour by
 // colour.  The Full kernel alternates between x and the level's second copy:
 // colour i reads one and writes the other, so after the 2^d colours (an even
-// number) the result is back in x.
+// number) the result is back in x.  from_zero: the step starts from x = 0
+// (pre-smoothing in the V-cycle); colour 0 then takes r = b and writes every
+// node, so x need not be cleared first.
 template <typename T>
-dgmg_status op_smooth(dgmg_ctx* c, int l, T* x, const T* b, int reverse, int nrhs) {
+dgmg_status op_smooth(dgmg_ctx* c, int l, T* x, const T* b, int reverse, int nrhs,
+                      bool from_zero = false) {
   const double sc = level_scale(c, l);
   const int nc = 1 << c->dim;
   const bool full = c->variant == DGMG_SMOOTH_FULL;
@@ -317,8 +320,9 @@ dgmg_status op_smooth(dgmg_ctx* c, int l, T* x, const T* b, int reverse, int nrh
     const auto& tu = c->tune_smooth[prec_index<T>()][l];
     g.xcd_remap = xcd_remap_flag(tu.remap);
     T* out = full ? other : cur;
-    HIPCHK(c, kset<T>(c).smooth[tu.shape](tab_of<T>(c), g, (T)sc, (T)(1.0 / sc), c->variant, cur, out,
-                                          b, nrhs, c->lv[l].ndof, c->stream));
+    const int zero = (from_zero && !reverse && i == 0) ? 1 : 0;
+    HIPCHK(c, kset<T>(c).smooth[tu.shape](tab_of<T>(c), g, (T)sc, (T)(1.0 / sc), c->variant, zero,
+                                          cur, out, b, nrhs, c->lv[l].ndof, c->stream));
     if (full) {
       other = cur;
       cur = out;
@@ -412,8 +416,7 @@ dgmg_status vcycle_T(dgmg_ctx* c, const T* bL, T* xL, int nrhs) {
   auto B = [&](int l) -> const T* { return l == L ? bL : lvb<T>(c->lv[l]); };
   auto X = [&](int l) -> T* { return l == L ? xL : lvx<T>(c->lv[l]); };
   for (int l = L; l >= 1; --l) {
-    RET(zero_vec<T>(c, X(l), c->lv[l].ndof * nrhs));
-    RET(op_smooth<T>(c, l, X(l), B(l), 0, nrhs));
+    RET(op_smooth<T>(c, l, X(l), B(l), 0, nrhs, true));
     RET(op_restrict<T>(c, l, X(l), B(l), lvb<T>(c->lv[l - 1]), nrhs));
   }
   RET(op_coarse<T>(c, B(0), X(0), nrhs));

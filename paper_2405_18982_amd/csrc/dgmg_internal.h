@@ -65,9 +65,11 @@ struct KernelSet {
   hipError_t (*mass)(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
                      long long ndof, hipStream_t s);
   // variant: DGMG_SMOOTH_* of the context.  The Dirichlet kernels update x in
-  // place (xin is ignored); the Full kernel reads xin and writes xout.
+  // place (xin is ignored); the Full kernel reads xin and writes xout.  zero:
+  // colour 0 of a step that starts from x = 0 (x is not read, every node of
+  // xout is written).
   hipError_t (*smooth[kSmoothShapes])(const void* tab, PatchGrid g, T scale, T inv_scale, int variant,
-                          const T* xin, T* xout, const T* b, int nrhs, long long ndof,
+                          int zero, const T* xin, T* xout, const T* b, int nrhs, long long ndof,
                           hipStream_t s);
   hipError_t (*restrict_residual)(const void* tab, PatchGrid g, T scale, const T* x, const T* b,
                                   T* bc, int nrhs, long long ndof, long long ndof_c,

@@ -752,7 +752,10 @@ k_mass(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restric
 //   MODE 4: clamped kernel: the residual from the patch cells alone (the
 //           terms it misses act on directions the clamped space annihilates),
 //           the FD solve on the clamped space; in place.
-template <typename T, int PPB, int MODE, bool PREFETCH>
+// ZERO: x = 0 on entry and the launch is colour 0, whose patches tile the mesh:
+// the residual is b itself (no operator pass, x is not read) and every tile
+// row is written (zeros outside V_j), so x needs no clearing beforehand.
+template <typename T, int PPB, int MODE, bool PREFETCH, bool ZERO = false>
 __global__ void __launch_bounds__(TPP * PPB)
 k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
          const T* __restrict__ xin, T* __restrict__ xout, const T* __restrict__ b, long long ndof) {
@@ -805,22 +808,37 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
   // kernels), and (PREFETCH) its line of b for the last operator pass: one
   // memory round trip less on the critical path of a patch, one tile more in
   // flight per patch
-  const Sides<T> ysd = (!FULL && active) ? yline_sides_global<T, OPM>(t, xr, g.N, P, lane % E, lane / E)
-                                         : Sides<T>{};
-  Line<T> bline;
-  if (PREFETCH && active) read_lastline<T>(br, g.N, P, lane, bline);
-
-  // residual r = b - A x on the last pass, contracted with S^T of that direction
-  operator_passes<T, OPM>(t, xr, g.N, P, A, B, ext, lane, active, xl, ysd,
-                          [&](int l, int base, int stride, const Line<T>& v) {
-                            Line<T> r, o;
-                            if (PREFETCH) r = bline;
-                            else read_lastline<T>(br, g.N, P, l, r);
+  if constexpr (ZERO) {
+    // r = b, contracted with S^T along the last direction
 #pragma unroll
-                            for (int p = 0; p < E; ++p) r.v[p] -= scale * v.v[p];
-                            line_St<T, SP>(t, (D == 3) ? tyz : tyy, r, o);
-                            store_line(A, base, stride, o);
-                          });
+    for (int p = 0; p < E; ++p) xl.v[p] = T(0);
+    if (active)
+      for (int i = lane; i < NL; i += TPP) {
+        int base, stride;
+        line_geom(D - 1, i, base, stride);
+        Line<T> r, o;
+        read_lastline<T>(br, g.N, P, i, r);
+        line_St<T, SP>(t, (D == 3) ? tyz : tyy, r, o);
+        store_line(A, base, stride, o);
+      }
+  } else {
+    const Sides<T> ysd = (!FULL && active) ? yline_sides_global<T, OPM>(t, xr, g.N, P, lane % E, lane / E)
+                                           : Sides<T>{};
+    Line<T> bline;
+    if (PREFETCH && active) read_lastline<T>(br, g.N, P, lane, bline);
+
+    // residual r = b - A x on the last pass, contracted with S^T of that direction
+    operator_passes<T, OPM>(t, xr, g.N, P, A, B, ext, lane, active, xl, ysd,
+                            [&](int l, int base, int stride, const Line<T>& v) {
+                              Line<T> r, o;
+                              if (PREFETCH) r = bline;
+                              else read_lastline<T>(br, g.N, P, l, r);
+#pragma unroll
+                              for (int p = 0; p < E; ++p) r.v[p] -= scale * v.v[p];
+                              line_St<T, SP>(t, (D == 3) ? tyz : tyy, r, o);
+                              store_line(A, base, stride, o);
+                            });
+  }
   __syncthreads();
   if constexpr (D == 3) {
     // X1: S_x^T
@@ -897,7 +915,7 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
   if (active) {
     for (int i = lane; i < NL; i += TPP) {
       const int py = i % E, pz = i / E;
-      const bool keep_line = FULL ||
+      const bool keep_line = FULL || ZERO ||
                              ((py > 0 || (tyy & 1)) && (py < E - 1 || (tyy & 2)) &&
                               (D == 2 || ((pz > 0 || (tyz & 1)) && (pz < E - 1 || (tyz & 2)))));
       if (!keep_line) continue;
@@ -1177,12 +1195,27 @@ hipError_t launch_mass(const void* tab, PatchGrid g, T scale, const T* x, T* y, 
 // variant 0 / 1 / 2 / 3: Dirichlet consistent / Dirichlet with the paper's
 // residual / Full / clamped
 template <typename T, int V>
-hipError_t launch_smooth(const void* tab, PatchGrid g, T scale, T inv_scale, int variant,
+hipError_t launch_smooth(const void* tab, PatchGrid g, T scale, T inv_scale, int variant, int zero,
                          const T* xin, T* xout, const T* b, int nrhs, long long ndof, hipStream_t s) {
   constexpr int PPB = Shape<(V & 1)>::PPB;
   constexpr bool PF = (V & 2) != 0;
   dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
   const Tab<K, T>* tb = (const Tab<K, T>*)tab;
+  if (zero) {  // x = 0, colour 0: the residual is b, no prefetch needed
+    if (variant == 2)
+      hipLaunchKernelGGL((k_smooth<T, PPB, 3, false, true>), grid, dim3(TPP * PPB), 0, s, tb, g,
+                         scale, inv_scale, xin, xout, b, ndof);
+    else if (variant == 3)
+      hipLaunchKernelGGL((k_smooth<T, PPB, 4, false, true>), grid, dim3(TPP * PPB), 0, s, tb, g,
+                         scale, inv_scale, xout, xout, b, ndof);
+    else if (variant == 1)
+      hipLaunchKernelGGL((k_smooth<T, PPB, 2, false, true>), grid, dim3(TPP * PPB), 0, s, tb, g,
+                         scale, inv_scale, xout, xout, b, ndof);
+    else
+      hipLaunchKernelGGL((k_smooth<T, PPB, 1, false, true>), grid, dim3(TPP * PPB), 0, s, tb, g,
+                         scale, inv_scale, xout, xout, b, ndof);
+    return hipGetLastError();
+  }
   if (variant == 2)
     hipLaunchKernelGGL((k_smooth<T, PPB, 3, PF>), grid, dim3(TPP * PPB), 0, s, tb, g, scale,
                        inv_scale, xin, xout, b, ndof);
