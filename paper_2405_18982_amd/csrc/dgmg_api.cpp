@@ -81,15 +81,7 @@ void fill_tab(const dgmg::HostTables& H, std::vector<unsigned char>& out) {
   using Tb = dgmg::Tab<K, T>;
   out.assign(sizeof(Tb), 0);
   Tb* t = reinterpret_cast<Tb*>(out.data());
-  constexpr int n = K + 1, E = 2 * n;
-  for (int i = 0; i < n * n; ++i) {
-    t->M[i] = (T)H.M[i];
-    t->Lc[i] = (T)H.Lc[i];
-  }
-  for (int i = 0; i < n; ++i) {
-    t->d0[i] = (T)H.d0[i];
-    t->d1[i] = (T)H.d1[i];
-  }
+  constexpr int E = 2 * (K + 1);
   t->sigma = (T)H.sigma;
   for (int ty = 0; ty < 4; ++ty) {
     for (int i = 0; i < E * E; ++i) t->S[ty][i] = (T)H.S[ty][i];
@@ -103,7 +95,6 @@ void fill_tab(const dgmg::HostTables& H, std::vector<unsigned char>& out) {
     for (int i = 0; i < E; ++i)
       t->lamc[ty][i] = std::isinf(H.lamc[ty][i]) ? (T)(sizeof(T) == 8 ? 1e300 : 1e30) : (T)H.lamc[ty][i];
   }
-  for (int i = 0; i < E * n; ++i) t->P[i] = (T)H.P[i];
 }
 
 template <typename T>

@@ -11,27 +11,21 @@ constexpr int kMaxDegree = 7;
 constexpr int kApplyShapes = 2;   // workgroup shapes of apply
 constexpr int kSmoothShapes = 4;  // workgroup shapes x prefetch of b for smooth
 
-// Reference (h = 1, kappa = 1) 1-D tables of Q_K on a two-cell patch, in the
-// arithmetic type T of the kernels that read them.  Built on the host in FP64
-// (setup.cpp) and uploaded once per context.
-//   M   : cell mass  int phi_mu phi_nu
-//   Lc  : 1-D SIPG cell block with interior faces on both sides
-//         K + sigma (e0 e0^T + e1 e1^T) + (e0 d0^T + d0 e0^T)/2 - (e1 d1^T + d1 e1^T)/2
-//   d0, d1 : phi'(0), phi'(1)
+// Reference (h = 1, kappa = 1) data of Q_K on a two-cell patch that depends
+// on the penalty, in the arithmetic type T of the kernels that read them.
+// Built on the host in FP64 (setup.cpp) and uploaded once per context.  (The
+// basis matrices that depend on K alone -- mass, stiffness, end derivatives,
+// prolongation -- are compile-time constants, dgmg_ref1d.h.)
+//   sigma : penalty factor (gamma_F = sigma / h)
 //   S[t], lam[t] : fast-diagonalisation eigenpairs of patch type t on the
 //         Dirichlet local space, padded to E (unused eigenvalue slots hold a
 //         huge finite value)
 //   Sf[t], lamf[t] : the same on the whole patch (Full kernel)
 //   Sc[t], lamc[t] : C S on the clamped space with basis C (clamped kernel)
-//   P   : stacked prolongation, P[(o n + mu) n + nu] = phi_nu((xi_mu + o)/2)
 template <int K, typename T>
 struct Tab {
   static constexpr int n = K + 1;
   static constexpr int E = 2 * n;
-  T M[n * n];
-  T Lc[n * n];
-  T d0[n];
-  T d1[n];
   T sigma;
   T S[4][E * E];
   T lam[4][E];
@@ -39,7 +33,6 @@ struct Tab {
   T lamf[4][E];
   T Sc[4][E * E];
   T lamc[4][E];
-  T P[E * n];
 };
 
 // The patches of one launch: patch m = (m_0, .., m_{D-1}), m_i < cnt[i], has

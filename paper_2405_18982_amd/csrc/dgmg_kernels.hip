@@ -32,6 +32,7 @@
 // giving the sum-factorised order
 //   a = M_x x, b = L_x x;  c = M_y b + L_y a, d = M_y a;  y = M_z c + L_z d.
 #include "dgmg_internal.h"
+#include "dgmg_ref1d.h"
 
 #ifndef DGMG_D
 #error "DGMG_D must be defined"
@@ -54,6 +55,10 @@ constexpr int SY = E + 1;                           // padded LDS strides
 constexpr int SZ = (D == 3) ? E * SY : 0;
 constexpr int TS = (D == 2) ? E * SY : E * SZ;      // padded tile size
 constexpr int NF = (D == 2) ? E : E * E;            // nodes of one patch face
+
+// Basis data of Q_K fixed at compile time (instruction immediates); only the
+// penalty and the patch eigenpairs come from the Tab struct.
+static constexpr ref1d::Ref<K> kRef = ref1d::make_ref<K>();
 
 // threads per patch (one per line) and patches per workgroup
 constexpr int TPP = NL;
@@ -97,7 +102,7 @@ __device__ __forceinline__ void line_mass(const Tab<K, T>* __restrict__ t, const
       if ((p == 0 && !need0) || (p == E - 1 && !needE)) continue;
       T s = T(0);
 #pragma unroll
-      for (int nu = 0; nu < n; ++nu) s += t->M[mu * n + nu] * v.v[c * n + nu];
+      for (int nu = 0; nu < n; ++nu) s += T(kRef.M[mu * n + nu]) * v.v[c * n + nu];
       o.v[p] = s;
     }
 }
@@ -141,7 +146,9 @@ __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const
       if ((p == 0 && !need0) || (p == E - 1 && !needE)) continue;
       T s = ACC ? o.v[p] : T(0);
 #pragma unroll
-      for (int nu = 0; nu < n; ++nu) s += t->Lc[mu * n + nu] * v.v[c * n + nu];
+      for (int nu = 0; nu < n; ++nu) s += T(kRef.Lcons[mu * n + nu]) * v.v[c * n + nu];
+      if (mu == 0) s += sg * v.v[c * n];          // penalty part of the cell block
+      if (mu == n - 1) s += sg * v.v[c * n + n - 1];
       o.v[p] = s;
     }
   // face between the two patch cells
@@ -150,21 +157,21 @@ __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const
   T gR = T(0), gL = T(0);
 #pragma unroll
   for (int j = 0; j < n; ++j) {
-    gR += t->d0[j] * v.v[n + j];
-    gL += t->d1[j] * v.v[j];
+    gR += T(kRef.d0[j]) * v.v[n + j];
+    gL += T(kRef.d1[j]) * v.v[j];
   }
   T aL = sd.aL, bL = sd.bL, aR = sd.aR, bR = sd.bR;
   if (sd.bl) {  // Nitsche correction of the left cell (uniform per patch)
     T g0 = T(0);
 #pragma unroll
-    for (int j = 0; j < n; ++j) g0 += t->d0[j] * v.v[j];
+    for (int j = 0; j < n; ++j) g0 += T(kRef.d0[j]) * v.v[j];
     aL = half * g0;
     bL = half * v.v[0];
   }
   if (sd.br) {
     T g1 = T(0);
 #pragma unroll
-    for (int j = 0; j < n; ++j) g1 += t->d1[j] * v.v[n + j];
+    for (int j = 0; j < n; ++j) g1 += T(kRef.d1[j]) * v.v[n + j];
     aR = -half * g1;
     bR = -half * v.v[E - 1];
   }
@@ -174,18 +181,18 @@ __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const
   const T bRc = -half * tL;  // beta seen by the right cell from its left neighbour
   if (need0) {
     o.v[0] += aL;
-    o.v[0] += t->d0[0] * bL + t->d1[0] * bLc;
+    o.v[0] += T(kRef.d0[0]) * bL + T(kRef.d1[0]) * bLc;
   }
   o.v[n - 1] += -sg * tR - half * gR;
   o.v[n] += half * gL - sg * tL;
   if (needE) {
     o.v[E - 1] += aR;
-    o.v[E - 1] += t->d0[n - 1] * bRc + t->d1[n - 1] * bR;
+    o.v[E - 1] += T(kRef.d0[n - 1]) * bRc + T(kRef.d1[n - 1]) * bR;
   }
 #pragma unroll
   for (int mu = 0; mu < n; ++mu) {
-    if (mu > 0) o.v[mu] += t->d0[mu] * bL + t->d1[mu] * bLc;
-    if (mu < n - 1) o.v[n + mu] += t->d0[mu] * bRc + t->d1[mu] * bR;
+    if (mu > 0) o.v[mu] += T(kRef.d0[mu]) * bL + T(kRef.d1[mu]) * bLc;
+    if (mu < n - 1) o.v[n + mu] += T(kRef.d0[mu]) * bRc + T(kRef.d1[mu]) * bR;
   }
 }
 
@@ -340,7 +347,7 @@ __device__ __forceinline__ Sides<T> xline_sides(const Tab<K, T>* __restrict__ t,
       if (MODE == 0) {
         T g = T(0);
 #pragma unroll
-        for (int j = 0; j < n; ++j) g += t->d1[j] * r[j];
+        for (int j = 0; j < n; ++j) g += T(kRef.d1[j]) * r[j];
         sd.aL = half * g - sg * tr;
       }
     }
@@ -351,7 +358,7 @@ __device__ __forceinline__ Sides<T> xline_sides(const Tab<K, T>* __restrict__ t,
       if (MODE == 0) {
         T g = T(0);
 #pragma unroll
-        for (int j = 0; j < n; ++j) g += t->d0[j] * r[j];
+        for (int j = 0; j < n; ++j) g += T(kRef.d0[j]) * r[j];
         sd.aR = -sg * tr - half * g;
       }
     }
@@ -395,7 +402,7 @@ __device__ __forceinline__ void gather_ext(const Tab<K, T>* __restrict__ t, cons
       if (MODE == 0) {
         T g = T(0);
 #pragma unroll
-        for (int j = 0; j < n; ++j) g += ((side == 0) ? t->d1[j] : t->d0[j]) * x[base + (long long)j * strideN];
+        for (int j = 0; j < n; ++j) g += ((side == 0) ? T(kRef.d1[j]) : T(kRef.d0[j])) * x[base + (long long)j * strideN];
         alpha = (side == 0) ? (half * g - sg * tr) : (-sg * tr - half * g);
       }
     }
@@ -415,7 +422,7 @@ __device__ __forceinline__ T ext_mx(const Tab<K, T>* __restrict__ t, const T* ar
   const int c0 = (a / n) * n, mu = a % n;
   T s = T(0);
 #pragma unroll
-  for (int nu = 0; nu < n; ++nu) s += t->M[mu * n + nu] * arr[c0 + nu + E * b];
+  for (int nu = 0; nu < n; ++nu) s += T(kRef.M[mu * n + nu]) * arr[c0 + nu + E * b];
   return s;
 }
 template <typename T>
@@ -423,7 +430,7 @@ __device__ __forceinline__ T ext_my(const Tab<K, T>* __restrict__ t, const T* ar
   const int c0 = (b / n) * n, mu = b % n;
   T s = T(0);
 #pragma unroll
-  for (int nu = 0; nu < n; ++nu) s += t->M[mu * n + nu] * arr[a + E * (c0 + nu)];
+  for (int nu = 0; nu < n; ++nu) s += T(kRef.M[mu * n + nu]) * arr[a + E * (c0 + nu)];
   return s;
 }
 
@@ -469,14 +476,14 @@ __device__ __forceinline__ Sides<T> yline_sides_global(const Tab<K, T>* __restri
     const T* r = x + cell_index(N, cx, P.lo[1] - 1, cz) * NC + K * n + az * n * n;
     T s = T(0);
 #pragma unroll
-    for (int nu = 0; nu < n; ++nu) s += t->M[mu * n + nu] * r[nu];
+    for (int nu = 0; nu < n; ++nu) s += T(kRef.M[mu * n + nu]) * r[nu];
     sd.bL = -half * s;
   }
   if (!sd.br) {
     const T* r = x + cell_index(N, cx, P.lo[1] + 2, cz) * NC + az * n * n;
     T s = T(0);
 #pragma unroll
-    for (int nu = 0; nu < n; ++nu) s += t->M[mu * n + nu] * r[nu];
+    for (int nu = 0; nu < n; ++nu) s += T(kRef.M[mu * n + nu]) * r[nu];
     sd.bR = half * s;
   }
   return sd;
@@ -974,7 +981,7 @@ k_restrict(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
                           for (int nu = 0; nu < n; ++nu) {
                             T s = T(0);
 #pragma unroll
-                            for (int p = 0; p < E; ++p) s += t->P[p * n + nu] * (r.v[p] - scale * v.v[p]);
+                            for (int p = 0; p < E; ++p) s += T(kRef.P[p * n + nu]) * (r.v[p] - scale * v.v[p]);
                             A[base + nu * stride] = s;
                           }
                         });
@@ -991,7 +998,7 @@ k_restrict(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
         for (int nu = 0; nu < n; ++nu) {
           T s = T(0);
 #pragma unroll
-          for (int p = 0; p < E; ++p) s += t->P[p * n + nu] * v.v[p];
+          for (int p = 0; p < E; ++p) s += T(kRef.P[p * n + nu]) * v.v[p];
           A[base + nu * stride] = s;
         }
       }
@@ -1011,7 +1018,7 @@ k_restrict(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
       for (int nu = 0; nu < n; ++nu) {
         T s = T(0);
 #pragma unroll
-        for (int p = 0; p < E; ++p) s += t->P[p * n + nu] * v.v[p];
+        for (int p = 0; p < E; ++p) s += T(kRef.P[p * n + nu]) * v.v[p];
         out[i * n + nu] = s;
       }
     }
@@ -1045,7 +1052,7 @@ k_prolong(const Tab<K, T>* __restrict__ t, PatchGrid g, const T* __restrict__ xc
       for (int p = 0; p < E; ++p) {
         T s = T(0);
 #pragma unroll
-        for (int nu = 0; nu < n; ++nu) s += t->P[p * n + nu] * v[nu];
+        for (int nu = 0; nu < n; ++nu) s += T(kRef.P[p * n + nu]) * v[nu];
         tile[base + p] = s;
       }
     }
@@ -1067,7 +1074,7 @@ k_prolong(const Tab<K, T>* __restrict__ t, PatchGrid g, const T* __restrict__ xc
         for (int p = 0; p < E; ++p) {
           T s = T(0);
 #pragma unroll
-          for (int nu = 0; nu < n; ++nu) s += t->P[p * n + nu] * v[nu];
+          for (int nu = 0; nu < n; ++nu) s += T(kRef.P[p * n + nu]) * v[nu];
           tile[base + p * stride] = s;
         }
       }

@@ -1,78 +1,21 @@
 // Host-side FP64 construction of the reference 1-D tables of the SIPG
-// multigrid (Sec. 2.2, Sec. 3.2, Appendix A): Gauss-Lobatto nodes, Lagrange
-// basis, cell mass/stiffness, the 1-D SIPG cell block, the embedding
-// prolongation, and the fast-diagonalisation eigenpairs L S = M S Lambda of
+// multigrid (Sec. 2.2, Sec. 3.2, Appendix A): the basis data of Q_k (the
+// compile-time tables of dgmg_ref1d.h: Gauss-Lobatto nodes, mass, stiffness,
+// end derivatives, prolongation), the 1-D SIPG cell block with the penalty,
+// and the fast-diagonalisation eigenpairs L S = M S Lambda of
 // the two-cell patch restricted to the Dirichlet local space, on the whole
 // patch (Full kernel) and on the clamped space, for each of the four 1-D
 // patch types.  Everything is computed at h = 1, kappa = 1; the
 // kernels scale by kappa h^(d-2).
 #include "dgmg_setup.h"
 
+#include "dgmg_ref1d.h"
+
 #include <cmath>
 #include <limits>
 
 namespace dgmg {
 namespace {
-
-// Legendre P_m(x) and P_m'(x) by the three-term recurrence.
-void legendre(int m, double x, double& p, double& dp) {
-  double p0 = 1.0, p1 = x;
-  if (m == 0) { p = 1.0; dp = 0.0; return; }
-  for (int j = 2; j <= m; ++j) {
-    const double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
-    p0 = p1;
-    p1 = p2;
-  }
-  p = p1;
-  // derivative from (1 - x^2) P_m' = m (P_{m-1} - x P_m), valid for |x| < 1
-  dp = m * (p0 - x * p1) / (1.0 - x * x);
-}
-
-// m-point Gauss-Legendre rule on [0,1]: Newton on P_m from Chebyshev guesses.
-void gauss01(int m, std::vector<double>& x, std::vector<double>& w) {
-  x.assign(m, 0.0);
-  w.assign(m, 0.0);
-  for (int j = 0; j < m; ++j) {
-    double t = -std::cos(M_PI * (j + 0.75) / (m + 0.5));
-    for (int it = 0; it < 100; ++it) {
-      double p, dp;
-      legendre(m, t, p, dp);
-      const double dt = p / dp;
-      t -= dt;
-      if (std::fabs(dt) < 1e-16) break;
-    }
-    double p, dp;
-    legendre(m, t, p, dp);
-    x[j] = 0.5 * (t + 1.0);
-    w[j] = 1.0 / ((1.0 - t * t) * dp * dp);  // 2/((1-t^2)P'^2) scaled by 1/2
-  }
-}
-
-// Lagrange basis values and derivatives at y: V[j] = phi_j(y), Dv[j] = phi_j'(y).
-void lagrange(const std::vector<double>& nd, double y, std::vector<double>& V,
-              std::vector<double>& Dv) {
-  const int n = (int)nd.size();
-  V.assign(n, 0.0);
-  Dv.assign(n, 0.0);
-  for (int j = 0; j < n; ++j) {
-    double den = 1.0;
-    for (int m = 0; m < n; ++m)
-      if (m != j) den *= nd[j] - nd[m];
-    double num = 1.0;
-    for (int m = 0; m < n; ++m)
-      if (m != j) num *= y - nd[m];
-    V[j] = num / den;
-    double ds = 0.0;
-    for (int l = 0; l < n; ++l) {
-      if (l == j) continue;
-      double pr = 1.0;
-      for (int m = 0; m < n; ++m)
-        if (m != j && m != l) pr *= y - nd[m];
-      ds += pr;
-    }
-    Dv[j] = ds / den;
-  }
-}
 
 // Cholesky A = C C^T of an SPD matrix (row-major, size m); false if not SPD.
 bool cholesky(const std::vector<double>& A, int m, std::vector<double>& C) {
@@ -240,25 +183,31 @@ std::vector<double> clamped_basis(int k, int t, const std::vector<double>& d0,
 
 }  // namespace
 
+template <int K>
+void copy_ref(HostTables& T) {
+  constexpr ref1d::Ref<K> R = ref1d::make_ref<K>();
+  constexpr int n = K + 1;
+  T.nodes.assign(R.nodes, R.nodes + n);
+  T.M.assign(R.M, R.M + n * n);
+  T.K.assign(R.Ks, R.Ks + n * n);
+  T.d0.assign(R.d0, R.d0 + n);
+  T.d1.assign(R.d1, R.d1 + n);
+  T.Lc.assign(R.Lcons, R.Lcons + n * n);
+  T.P.assign(R.P, R.P + 2 * n * n);
+}
+
 std::vector<double> gll_nodes01(int k) {
-  std::vector<double> x(k + 1);
-  x[0] = 0.0;
-  x[k] = 1.0;
-  // interior points: roots of P_k', Newton on P_k' with P_k'' from the
-  // Legendre equation (1-t^2) P'' = 2 t P' - k(k+1) P
-  for (int j = 1; j < k; ++j) {
-    double t = -std::cos(M_PI * j / k);
-    for (int it = 0; it < 100; ++it) {
-      double p, dp;
-      legendre(k, t, p, dp);
-      const double d2p = (2.0 * t * dp - k * (k + 1.0) * p) / (1.0 - t * t);
-      const double dt = dp / d2p;
-      t -= dt;
-      if (std::fabs(dt) < 1e-16) break;
-    }
-    x[j] = 0.5 * (t + 1.0);
+  HostTables T;
+  switch (k) {
+    case 1: copy_ref<1>(T); break;
+    case 2: copy_ref<2>(T); break;
+    case 3: copy_ref<3>(T); break;
+    case 4: copy_ref<4>(T); break;
+    case 5: copy_ref<5>(T); break;
+    case 6: copy_ref<6>(T); break;
+    default: copy_ref<7>(T); break;
   }
-  return x;
+  return T.nodes;
 }
 
 bool build_host_tables(int k, double sigma, HostTables& T, const char** err) {
@@ -267,39 +216,20 @@ bool build_host_tables(int k, double sigma, HostTables& T, const char** err) {
   T.n = n;
   T.E = E;
   T.sigma = sigma;
-  T.nodes = gll_nodes01(k);
-  std::vector<double> xq, wq, V, Dv;
-  gauss01(n, xq, wq);  // exact for degree 2k+1
-  T.M.assign(n * n, 0.0);
-  T.K.assign(n * n, 0.0);
-  for (int q = 0; q < n; ++q) {
-    lagrange(T.nodes, xq[q], V, Dv);
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        T.M[i * n + j] += wq[q] * V[i] * V[j];
-        T.K[i * n + j] += wq[q] * Dv[i] * Dv[j];
-      }
+  switch (k) {  // basis data of Q_k (compile-time tables shared with the kernels)
+    case 1: copy_ref<1>(T); break;
+    case 2: copy_ref<2>(T); break;
+    case 3: copy_ref<3>(T); break;
+    case 4: copy_ref<4>(T); break;
+    case 5: copy_ref<5>(T); break;
+    case 6: copy_ref<6>(T); break;
+    case 7: copy_ref<7>(T); break;
+    default: *err = "degree out of range"; return false;
   }
-  lagrange(T.nodes, 0.0, V, T.d0);
-  lagrange(T.nodes, 1.0, V, T.d1);
-  // 1-D SIPG cell block with interior faces at both ends (h = 1):
-  // K + sigma(e0 e0^T + e1 e1^T) + (e0 d0^T + d0 e0^T)/2 - (e1 d1^T + d1 e1^T)/2
-  T.Lc = T.K;
+  // 1-D SIPG cell block with interior faces at both ends (h = 1): the
+  // consistency part plus the penalty sigma (e0 e0^T + e1 e1^T)
   T.Lc[0] += sigma;
   T.Lc[k * n + k] += sigma;
-  for (int j = 0; j < n; ++j) {
-    T.Lc[0 * n + j] += 0.5 * T.d0[j];
-    T.Lc[j * n + 0] += 0.5 * T.d0[j];
-    T.Lc[k * n + j] -= 0.5 * T.d1[j];
-    T.Lc[j * n + k] -= 0.5 * T.d1[j];
-  }
-  // stacked prolongation P[(o n + mu) n + nu] = phi_nu((xi_mu + o)/2)
-  T.P.assign(E * n, 0.0);
-  for (int o = 0; o < 2; ++o)
-    for (int mu = 0; mu < n; ++mu) {
-      lagrange(T.nodes, 0.5 * (T.nodes[mu] + o), V, Dv);
-      for (int nu = 0; nu < n; ++nu) T.P[(o * n + mu) * n + nu] = V[nu];
-    }
   // two-cell patch 1-D matrices: cell blocks Lc, the coupling across the
   // middle face, and the Nitsche corrections of the boundary types
   std::vector<double> Lp(E * E, 0.0), Mp(E * E, 0.0);
