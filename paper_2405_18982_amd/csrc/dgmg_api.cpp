@@ -135,6 +135,9 @@ struct dgmg_ctx {
   // the caller's stream.  Captured on the library's own stream (default
   // priority); invalidated when kappa changes.
   bool use_graph = true;
+  // levels 1 and 0 of the V-cycle in one launch where the kernels allow it
+  // (DGMG_FUSE_BOTTOM=0 at set-up turns it off, to measure its effect)
+  bool fuse_bottom = true;
   // workgroup shape and XCD-aware numbering of the tuned kernels, per
   // precision (0: FP64, 1: FP32); set by dgmg_autotune
   struct Tuning {
@@ -406,12 +409,22 @@ dgmg_status vcycle_T(dgmg_ctx* c, const T* bL, T* xL, int nrhs) {
   const int L = c->L;
   auto B = [&](int l) -> const T* { return l == L ? bL : lvb<T>(c->lv[l]); };
   auto X = [&](int l) -> T* { return l == L ? xL : lvx<T>(c->lv[l]); };
-  for (int l = L; l >= 1; --l) {
+  // levels 1 and 0 in one launch (same arithmetic as the separate kernels)
+  const bool fuse = c->fuse_bottom && kset<T>(c).bottom && c->variant != DGMG_SMOOTH_FULL;
+  const int lo = fuse ? 2 : 1;
+  for (int l = L; l >= lo; --l) {
     RET(op_smooth<T>(c, l, X(l), B(l), 0, nrhs, true));
     RET(op_restrict<T>(c, l, X(l), B(l), lvb<T>(c->lv[l - 1]), nrhs));
   }
-  RET(op_coarse<T>(c, B(0), X(0), nrhs));
-  for (int l = 1; l <= L; ++l) {
+  if (fuse) {
+    const double s1 = level_scale(c, 1);
+    HIPCHK(c, kset<T>(c).bottom(tab_of<T>(c), c->variant, (T)s1, (T)(1.0 / s1),
+                                (T)(1.0 / level_scale(c, 0)), X(1), B(1), lvb<T>(c->lv[0]),
+                                X(0), nrhs, c->lv[1].ndof, c->lv[0].ndof, c->stream));
+  } else {
+    RET(op_coarse<T>(c, B(0), X(0), nrhs));
+  }
+  for (int l = lo; l <= L; ++l) {
     RET(op_prolong<T>(c, l, X(l - 1), X(l), nrhs));
     RET(op_smooth<T>(c, l, X(l), B(l), 1, nrhs));
   }
@@ -528,6 +541,10 @@ DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int sm
   if (nrhs_max < 1 || nrhs_max > 4096) return fail(c, DGMG_ERR_ARG, "nrhs_max out of range");
   c->prec = vcycle_precision;
   c->variant = smoother_variant;
+  {
+    const char* e = std::getenv("DGMG_FUSE_BOTTOM");
+    c->fuse_bottom = !(e && e[0] == '0');
+  }
   c->nrhs_max = nrhs_max;
   c->stream = (hipStream_t)hip_stream;
   std::vector<unsigned char> t64, t32;

@@ -71,6 +71,12 @@ struct KernelSet {
                                long long ndof, long long ndof_c, hipStream_t s);
   hipError_t (*coarse)(const void* tab, T inv_scale, const T* b, T* x, int nrhs,
                        long long ndof, hipStream_t s);
+  // levels 1 and 0 of the V-cycle in one launch (pre-smoothing from zero,
+  // restriction, coarse solve, prolongation, post-smoothing); null where the
+  // level-1 patches of a colour do not fit one workgroup
+  hipError_t (*bottom)(const void* tab, int variant, T scale1, T inv_scale1, T inv_scale0, T* x1,
+                       const T* b1, T* b0, T* x0, int nrhs, long long ndof1, long long ndof0,
+                       hipStream_t s);
 };
 
 // Registration entry of one kernel translation unit.

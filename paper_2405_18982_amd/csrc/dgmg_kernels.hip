@@ -762,25 +762,29 @@ k_mass(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restric
 // ZERO: x = 0 on entry and the launch is colour 0, whose patches tile the mesh:
 // the residual is b itself (no operator pass, x is not read) and every tile
 // row is written (zeros outside V_j), so x needs no clearing beforehand.
-template <typename T, int PPB, int MODE, bool PREFETCH, bool ZERO = false>
-__global__ void __launch_bounds__(TPP * PPB)
-k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
-         const T* __restrict__ xin, T* __restrict__ xout, const T* __restrict__ b, long long ndof) {
+// LDS per patch of the smoother: operator face data (full rows) for the Full
+// kernel, z-face traces only for the Dirichlet and clamped kernels
+template <int MODE>
+__host__ __device__ constexpr int smooth_pp() {
+  return MODE == 3 ? Smem<2, (D - 1) * 2 * 2 * NF>::per_patch : Smem<2, (D - 2) * 2 * NF>::per_patch;
+}
+
+// One patch (pid of grid g, right-hand side rhs) of one colour; lane = thread
+// within the patch, sm = the patch's LDS.  Every thread of the workgroup calls
+// this (barriers inside), with pid >= g.npatch for idle slots.
+template <typename T, int MODE, bool PREFETCH, bool ZERO>
+__device__ __forceinline__ void smooth_body(const Tab<K, T>* __restrict__ t, const PatchGrid& g, T scale,
+                                            T inv_scale, const T* __restrict__ xin, T* __restrict__ xout,
+                                            const T* __restrict__ b, long long ndof, int pid, int lane,
+                                            T* sm, int rhs) {
   constexpr bool FULL = (MODE == 3);
   constexpr int SP = FULL ? SP_FULL : (MODE == 4) ? SP_CLAMPED : SP_DIR;
   constexpr int OPM = FULL ? 0 : (MODE == 4) ? 2 : MODE;  // operator-pass mode (side data)
-  // operator face data (full rows) for the Full kernel, z-face traces only
-  // for the Dirichlet kernels
-  constexpr int PP = FULL ? Smem<2, (D - 1) * 2 * 2 * NF>::per_patch
-                          : Smem<2, (D - 2) * 2 * NF>::per_patch;
-  __shared__ T smem[PPB * PP];
-  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
-  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
   const bool inrange = pid < g.npatch;
-  T* A = smem + slot * PP;
+  T* A = sm;
   T* B = A + TS;
   T* ext = B + TS;
-  const long long roff = (long long)blockIdx.y * ndof;
+  const long long roff = (long long)rhs * ndof;
   T* xw = xout + roff;
   const T* xr = (FULL ? xin : xout) + roff;
   const T* br = b + roff;
@@ -953,23 +957,34 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
   }
 }
 
+template <typename T, int PPB, int MODE, bool PREFETCH, bool ZERO = false>
+__global__ void __launch_bounds__(TPP * PPB)
+k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
+         const T* __restrict__ xin, T* __restrict__ xout, const T* __restrict__ b, long long ndof) {
+  constexpr int PP = smooth_pp<MODE>();
+  __shared__ T smem[PPB * PP];
+  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
+  smooth_body<T, MODE, PREFETCH, ZERO>(t, g, scale, inv_scale, xin, xout, b, ndof, pid, lane,
+                                       smem + slot * PP, blockIdx.y);
+}
+
 // ------------------------------------------------- residual + restriction
 // bc = P^T (b - A x): the colour-0 patch of level l is the set of children of
 // one coarse cell, so its residual contracts with the stacked P^T per
 // direction straight into that coarse cell.
-template <typename T, int PPB>
-__global__ void __launch_bounds__(TPP * PPB)
-k_restrict(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
-           const T* __restrict__ b, T* __restrict__ bc, long long ndof, long long ndof_c) {
-  constexpr int PP = Smem<2, (D - 1) * 2 * 2 * NF>::per_patch;
-  __shared__ T smem[PPB * PP];
-  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
-  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
+constexpr int kRestrictPP = Smem<2, (D - 1) * 2 * 2 * NF>::per_patch;
+
+template <typename T>
+__device__ __forceinline__ void restrict_body(const Tab<K, T>* __restrict__ t, const PatchGrid& g, T scale,
+                                              const T* __restrict__ x, const T* __restrict__ b,
+                                              T* __restrict__ bc, long long ndof, long long ndof_c,
+                                              int pid, int lane, T* sm, int rhs) {
   const bool active = pid < g.npatch;
-  T* A = smem + slot * PP;
+  T* A = sm;
   T* B = A + TS;
   T* ext = B + TS;
-  const long long roff = (long long)blockIdx.y * ndof;
+  const long long roff = (long long)rhs * ndof;
   const PatchPos P = patch_pos(g, active ? pid : 0);
   Line<T> xl;
   Sides<T> ysd{};
@@ -1008,7 +1023,7 @@ k_restrict(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
   if (active) {
     const int Nc = g.N / 2;
     const long long cell = cell_index(Nc, P.lo[0] / 2, P.lo[1] / 2, (D == 3) ? P.lo[2] / 2 : 0);
-    T* out = bc + (long long)blockIdx.y * ndof_c + cell * NC;
+    T* out = bc + (long long)rhs * ndof_c + cell * NC;
     for (int i = lane; i < NC / n; i += TPP) {
       const int py = i % n, pz = i / n;
       const int base = py * SY + pz * SZ;
@@ -1025,23 +1040,29 @@ k_restrict(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
   }
 }
 
-// ------------------------------------------------- prolongation + add
 template <typename T, int PPB>
 __global__ void __launch_bounds__(TPP * PPB)
-k_prolong(const Tab<K, T>* __restrict__ t, PatchGrid g, const T* __restrict__ xc,
-          T* __restrict__ x, long long ndof, long long ndof_c) {
-  __shared__ T smem[PPB * TS];
+k_restrict(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
+           const T* __restrict__ b, T* __restrict__ bc, long long ndof, long long ndof_c) {
+  __shared__ T smem[PPB * kRestrictPP];
   const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
   const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
+  restrict_body<T>(t, g, scale, x, b, bc, ndof, ndof_c, pid, lane, smem + slot * kRestrictPP, blockIdx.y);
+}
+
+// ------------------------------------------------- prolongation + add
+template <typename T>
+__device__ __forceinline__ void prolong_body(const PatchGrid& g, const T* __restrict__ xc, T* __restrict__ x,
+                                             long long ndof, long long ndof_c, int pid, int lane, T* tile,
+                                             int rhs) {
   const bool active = pid < g.npatch;
-  T* tile = smem + slot * TS;
   const PatchPos P = patch_pos(g, active ? pid : 0);
-  const long long roff = (long long)blockIdx.y * ndof;
+  const long long roff = (long long)rhs * ndof;
   // along x: coarse rows (ly, lz) straight from global
   if (active) {
     const int Nc = g.N / 2;
     const long long cell = cell_index(Nc, P.lo[0] / 2, P.lo[1] / 2, (D == 3) ? P.lo[2] / 2 : 0);
-    const T* in = xc + (long long)blockIdx.y * ndof_c + cell * NC;
+    const T* in = xc + (long long)rhs * ndof_c + cell * NC;
     for (int i = lane; i < NC / n; i += TPP) {
       const int py = i % n, pz = i / n;
       const int base = py * SY + pz * SZ;
@@ -1096,20 +1117,32 @@ k_prolong(const Tab<K, T>* __restrict__ t, PatchGrid g, const T* __restrict__ xc
   }
 }
 
+template <typename T, int PPB>
+__global__ void __launch_bounds__(TPP * PPB)
+k_prolong(const Tab<K, T>* __restrict__ t, PatchGrid g, const T* __restrict__ xc,
+          T* __restrict__ x, long long ndof, long long ndof_c) {
+  __shared__ T smem[PPB * TS];
+  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
+  (void)t;
+  prolong_body<T>(g, xc, x, ndof, ndof_c, pid, lane, smem + slot * TS, blockIdx.y);
+}
+
 // ---------------------------------------------------------- coarse solve
 // Level 0 (N = 2): one patch, every node kept (type 3 in all directions).
+// Every thread of the workgroup calls this (barriers inside); only threads
+// with active set work.
 template <typename T>
-__global__ void __launch_bounds__(TPP)
-k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, T* __restrict__ x,
-         long long ndof) {
-  __shared__ T tile[TS];
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void coarse_body(const Tab<K, T>* __restrict__ t, T inv_scale,
+                                            const T* __restrict__ b, T* __restrict__ x, long long ndof,
+                                            int lane, T* tile, int rhs, bool active) {
   PatchPos P;
 #pragma unroll
   for (int i = 0; i < 3; ++i) { P.lo[i] = 0; P.ty[i] = 3; }
-  const long long roff = (long long)blockIdx.y * ndof;
+  const long long roff = (long long)rhs * ndof;
+  const int nl = active ? NL : 0;  // lines this thread's patch slot works on
   // S_x^T straight from the rows of b
-  for (int i = lane; i < NL; i += TPP) {
+  for (int i = lane; i < nl; i += TPP) {
     const int py = i % E, pz = i / E;
     int base, stride;
     line_geom(0, i, base, stride);
@@ -1122,7 +1155,7 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
   // S^T along the remaining directions; the last one also scales and applies S
 #pragma unroll
   for (int dir = 1; dir < D; ++dir) {
-    for (int i = lane; i < NL; i += TPP) {
+    for (int i = lane; i < nl; i += TPP) {
       int base, stride;
       line_geom(dir, i, base, stride);
       Line<T> v, o;
@@ -1144,7 +1177,7 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
   // S along the directions before the last, ending with x as contiguous rows
 #pragma unroll
   for (int dir = D - 2; dir >= 1; --dir) {
-    for (int i = lane; i < NL; i += TPP) {
+    for (int i = lane; i < nl; i += TPP) {
       int base, stride;
       line_geom(dir, i, base, stride);
       Line<T> v, o;
@@ -1154,7 +1187,7 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
     }
     __syncthreads();
   }
-  for (int i = lane; i < NL; i += TPP) {
+  for (int i = lane; i < nl; i += TPP) {
     const int py = i % E, pz = i / E;
     int base, stride;
     line_geom(0, i, base, stride);
@@ -1167,6 +1200,83 @@ k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, 
       x[row0 + a] = o.v[a];
       x[row0 + NC + a] = o.v[n + a];
     }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPP)
+k_coarse(const Tab<K, T>* __restrict__ t, T inv_scale, const T* __restrict__ b, T* __restrict__ x,
+         long long ndof) {
+  __shared__ T tile[TS];
+  coarse_body<T>(t, inv_scale, b, x, ndof, threadIdx.x, tile, blockIdx.y, true);
+}
+
+// ------------------------------------------------------- V-cycle bottom
+// Levels 1 (N = 4) and 0 (N = 2) of the V-cycle in one workgroup per
+// right-hand side.  A colour of level 1 has at most 2^D patches, one patch
+// slot each, so colours follow each other at a barrier instead of a launch:
+// pre-smoothing from x = 0 (colours ascending), residual + restriction, the
+// exact coarse solve, prolongation + add, post-smoothing (descending).  Every
+// patch does the arithmetic of the separate kernels.  In-place smoothers only.
+constexpr int kBottomSlots = 1 << D;
+constexpr int kBottomPP = kRestrictPP > smooth_pp<1>() ? kRestrictPP : smooth_pp<1>();
+
+template <typename T>
+constexpr bool bottom_fits() {
+  return TPP * kBottomSlots <= 1024 && kBottomSlots * kBottomPP * (int)sizeof(T) <= 160 * 1024;
+}
+
+__device__ __forceinline__ PatchGrid level1_colour(int colour) {
+  PatchGrid g{};
+  g.N = 4;
+  g.xcd_remap = 0;
+  g.npatch = 1;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int bit = (i < D) ? (colour >> i) & 1 : 0;
+    g.off[i] = bit;
+    g.cnt[i] = (i < D) ? (bit ? 1 : 2) : 1;
+    g.npatch *= g.cnt[i];
+  }
+  return g;
+}
+
+template <typename T>
+struct BottomArgs {
+  T scale1, inv_scale1, scale0_inv;
+  T* x1;
+  const T* b1;
+  T* b0;
+  T* x0;
+  long long ndof1, ndof0;
+};
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TPP * kBottomSlots)
+k_bottom(const Tab<K, T>* __restrict__ t, BottomArgs<T> a) {
+  __shared__ T smem[kBottomSlots * kBottomPP];
+  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  T* sm = smem + slot * kBottomPP;
+  const int rhs = blockIdx.y;
+  constexpr int NCOL = 1 << D;
+  smooth_body<T, MODE, false, true>(t, level1_colour(0), a.scale1, a.inv_scale1, a.x1, a.x1, a.b1,
+                                    a.ndof1, slot, lane, sm, rhs);
+  __syncthreads();
+  for (int c = 1; c < NCOL; ++c) {
+    smooth_body<T, MODE, false, false>(t, level1_colour(c), a.scale1, a.inv_scale1, a.x1, a.x1, a.b1,
+                                       a.ndof1, slot, lane, sm, rhs);
+    __syncthreads();
+  }
+  restrict_body<T>(t, level1_colour(0), a.scale1, a.x1, a.b1, a.b0, a.ndof1, a.ndof0, slot, lane, sm, rhs);
+  __syncthreads();
+  coarse_body<T>(t, a.scale0_inv, a.b0, a.x0, a.ndof0, lane, sm, rhs, slot == 0);
+  __syncthreads();
+  prolong_body<T>(level1_colour(0), a.x0, a.x1, a.ndof1, a.ndof0, slot, lane, sm, rhs);
+  __syncthreads();
+  for (int c = NCOL - 1; c >= 0; --c) {
+    smooth_body<T, MODE, false, false>(t, level1_colour(c), a.scale1, a.inv_scale1, a.x1, a.x1, a.b1,
+                                       a.ndof1, slot, lane, sm, rhs);
+    __syncthreads();
   }
 }
 
@@ -1264,6 +1374,25 @@ hipError_t launch_coarse(const void* tab, T inv_scale, const T* b, T* x, int nrh
   return hipGetLastError();
 }
 
+// variant 0 / 1 / 3 (in-place smoothers); the Full kernel is not fused
+template <typename T>
+hipError_t launch_bottom(const void* tab, int variant, T scale1, T inv_scale1, T inv_scale0, T* x1,
+                         const T* b1, T* b0, T* x0, int nrhs, long long ndof1, long long ndof0,
+                         hipStream_t s) {
+  if constexpr (!bottom_fits<T>()) {
+    return hipErrorInvalidConfiguration;
+  } else {
+    const BottomArgs<T> a{scale1, inv_scale1, inv_scale0, x1, b1, b0, x0, ndof1, ndof0};
+    const Tab<K, T>* tb = (const Tab<K, T>*)tab;
+    const dim3 grid(1, nrhs), block(TPP * kBottomSlots);
+    if (variant == 0) hipLaunchKernelGGL((k_bottom<T, 1>), grid, block, 0, s, tb, a);
+    else if (variant == 1) hipLaunchKernelGGL((k_bottom<T, 2>), grid, block, 0, s, tb, a);
+    else if (variant == 3) hipLaunchKernelGGL((k_bottom<T, 4>), grid, block, 0, s, tb, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+}
+
 template <typename T>
 KernelSet<T> make_set() {
   KernelSet<T> k;
@@ -1277,6 +1406,7 @@ KernelSet<T> make_set() {
   k.restrict_residual = &launch_restrict<T>;
   k.prolongate_add = &launch_prolong<T>;
   k.coarse = &launch_coarse<T>;
+  k.bottom = bottom_fits<T>() ? &launch_bottom<T> : nullptr;
   return k;
 }
 

@@ -323,3 +323,27 @@ def test_graph_replays_equal_eager(precision):
             prob.apply(B[rep].contiguous(), out=y)  # eager work between replays
             torch.cuda.synchronize()
     prob.close()
+
+
+@pytest.mark.parametrize("dim,k,L,precision,variant", [
+    (2, 2, 1, 64, 0), (2, 5, 3, 64, 0), (3, 1, 2, 64, 0), (3, 2, 1, 64, 0), (3, 3, 3, 64, 0),
+    (3, 3, 2, 32, 0), (3, 4, 2, 32, 0), (3, 3, 2, 64, 1), (3, 3, 2, 64, 3), (3, 4, 1, 64, 0)])
+def test_fused_vcycle_bottom_equals_separate_kernels(monkeypatch, dim, k, L, precision, variant):
+    """Levels 1 and 0 in one launch give bitwise the V-cycle of the separate
+    kernels (where the kernels allow the fusion; elsewhere both paths are the
+    separate kernels)."""
+    note(f"fused bottom d={dim} k={k} L={L} fp{precision} variant={variant}")
+    outs = {}
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("DGMG_FUSE_BOTTOM", fuse)
+        prob = dgmg.Problem(dim, k, L, precision=precision, variant=variant, nrhs_max=2)
+        B = inputs.uniform(33, (2, prob.ndofs()))
+        dt = torch.float64 if precision == 64 else torch.float32
+        res = [prob.vcycle(cuda(B, dt)).clone()]
+        if variant != 1:  # the paper's residual makes the V-cycle unsymmetric (no CG)
+            res.append(prob.solve(cuda(B), rtol=1e-10, maxit=200)[0].clone())
+        outs[fuse] = res
+        prob.close()
+    torch.cuda.synchronize()
+    for a, b in zip(outs["1"], outs["0"]):
+        assert torch.equal(a, b)
