@@ -86,3 +86,29 @@ def test_gmres_reports_nonconvergence_and_zero_rhs():
     with pytest.raises(dgmg.DGMGError):
         prob.gmres(b, maxit=0)
     prob.close()
+
+
+def test_gmres_full_size_poisson3d_q3_32c():
+    """The bench workload (3-D Q3, 32^3 cells, 2.1M DoFs) with f = 1: the GPU
+    GMRES history step by step against the oracle's GMRES (FD smoother,
+    matrix-free operator) and the solution against the exact discrete one."""
+    from oracle.fdsolve import GlobalFD
+    note("gmres full size 3-D Q3 32^3")
+    w = inputs.WORKLOADS["poisson3d_q3_32c"]
+    dim, k, L = w["dim"], w["k"], w["L"]
+    sigma = inputs.sigma_of(k)
+    N = 2 ** (L + 1)
+    prob = dgmg.Problem(dim, k, L, sigma=sigma)
+    b = load_vector(dim, k, N, one)
+    x, m, hist = prob.gmres(torch.from_numpy(b).cuda(), rtol=1e-8, maxit=40)
+    X = x.cpu().numpy()
+    prob.close()
+    H = Hierarchy(dim, k, L, sigma)
+    xo, mo, ho = gmres(H.apply[L], H.vcycle, b, rtol=1e-8, maxit=40)
+    ho = np.array(ho)
+    assert m == mo, (m, mo)
+    assert np.all(np.abs(hist - ho) <= 1e-9 + 1e-6 * ho), np.c_[hist, ho]
+    u = GlobalFD(dim, k, N, sigma).solve(b)
+    assert np.linalg.norm(X - u) <= 1e-6 * np.linalg.norm(u)
+    assert np.linalg.norm(X - xo) <= 1e-9 * np.linalg.norm(xo)
+    note(f"  steps {m}, nu {fractional_iterations(hist):.3f}")
