@@ -1022,7 +1022,9 @@ void write_cache(const char* path, const std::vector<CacheEntry>& es) {
 template <typename T>
 dgmg_status tune_kernel(dgmg_ctx* c, int nrhs, bool smooth, int level, T* x, T* y,
                         dgmg_ctx::Tuning& slot) {
-  const int nshapes = smooth ? dgmg::kSmoothShapes : dgmg::kApplyShapes;
+  int nshapes = smooth ? dgmg::kSmoothShapes : dgmg::kApplyShapes;
+  if (smooth && (!kset<T>(c).smooth_split || c->variant == DGMG_SMOOTH_FULL))
+    nshapes = dgmg::kSmoothShapes / 2;  // the two-wave shapes would repeat the others
   const int reps = smooth ? 3 : 20;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));

@@ -41,6 +41,12 @@
 #error "DGMG_K must be defined"
 #endif
 
+// Multiply-adds are fused only within one expression (never across
+// statements), so every kernel variant that writes an output with the same
+// expressions -- one or two waves per patch, fused or separate launches --
+// computes it bit for bit alike, whatever the surrounding control flow.
+#pragma clang fp contract(on)
+
 namespace dgmg {
 namespace {
 
@@ -969,6 +975,392 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
                                        smem + slot * PP, blockIdx.y);
 }
 
+
+// ----------------------------------------------- split smoother (3-D)
+// The same colour step with two waves per patch (TPP a multiple of 64): wave h
+// of a patch owns, for every tile line, the outputs of cell h (indices
+// h n .. h n + n - 1) -- or the eigen-coefficients q in that range in the
+// fast-diagonalisation contractions -- while both waves read whole lines.
+// The 1-D coefficients a wave needs stay wave-uniform, each output element is
+// computed with the operations of the one-wave kernel in the same order (so
+// the results are bitwise those of k_smooth), and a patch occupies twice the
+// waves for the same LDS: more waves per SIMD to hide each other's latency.
+// Phases that rewrite the tile they read put a barrier between the reads of
+// both waves and the writes.
+template <typename T>
+struct Half {
+  T v[n];
+};
+
+template <int H>
+__device__ __forceinline__ constexpr bool half_end(int mu) { return H == 0 ? mu == 0 : mu == n - 1; }
+
+// o = (blockdiag(M, M) v) on cell H; the patch-end output only if needEnd
+template <typename T, int H>
+__device__ __forceinline__ void half_mass(const Line<T>& v, Half<T>& o, bool needEnd) {
+#pragma unroll
+  for (int mu = 0; mu < n; ++mu) {
+    if (half_end<H>(mu) && !needEnd) continue;
+    T s = T(0);
+#pragma unroll
+    for (int nu = 0; nu < n; ++nu) s += T(kRef.M[mu * n + nu]) * v.v[H * n + nu];
+    o.v[mu] = s;
+  }
+}
+
+// o (+)= 1-D SIPG of the patch line v on cell H (the rows of line_sipg, in
+// its order of operations)
+template <typename T, int H, bool ACC>
+__device__ __forceinline__ void half_sipg(const Tab<K, T>* __restrict__ t, const Line<T>& v,
+                                          const Sides<T>& sd, Half<T>& o, bool needEnd) {
+  const T sg = t->sigma;
+  const T half = T(0.5);
+#pragma unroll
+  for (int mu = 0; mu < n; ++mu) {
+    if (half_end<H>(mu) && !needEnd) continue;
+    T s = ACC ? o.v[mu] : T(0);
+#pragma unroll
+    for (int nu = 0; nu < n; ++nu) s += T(kRef.Lcons[mu * n + nu]) * v.v[H * n + nu];
+    if (mu == 0) s += sg * v.v[H * n];
+    if (mu == n - 1) s += sg * v.v[H * n + n - 1];
+    o.v[mu] = s;
+  }
+  if constexpr (H == 0) {
+    const T tR = v.v[n];
+    T gR = T(0);
+#pragma unroll
+    for (int j = 0; j < n; ++j) gR += T(kRef.d0[j]) * v.v[n + j];
+    T aL = sd.aL, bL = sd.bL;
+    if (sd.bl) {
+      T g0 = T(0);
+#pragma unroll
+      for (int j = 0; j < n; ++j) g0 += T(kRef.d0[j]) * v.v[j];
+      aL = half * g0;
+      bL = half * v.v[0];
+    }
+    if (!sd.bl && sd.lit) bL = -half * v.v[0];
+    const T bLc = half * tR;
+    if (needEnd) {
+      o.v[0] += aL;
+      o.v[0] += T(kRef.d0[0]) * bL + T(kRef.d1[0]) * bLc;
+    }
+    o.v[n - 1] += -sg * tR - half * gR;
+#pragma unroll
+    for (int mu = 1; mu < n; ++mu) o.v[mu] += T(kRef.d0[mu]) * bL + T(kRef.d1[mu]) * bLc;
+  } else {
+    const T tL = v.v[n - 1];
+    T gL = T(0);
+#pragma unroll
+    for (int j = 0; j < n; ++j) gL += T(kRef.d1[j]) * v.v[j];
+    T aR = sd.aR, bR = sd.bR;
+    if (sd.br) {
+      T g1 = T(0);
+#pragma unroll
+      for (int j = 0; j < n; ++j) g1 += T(kRef.d1[j]) * v.v[n + j];
+      aR = -half * g1;
+      bR = -half * v.v[E - 1];
+    }
+    if (!sd.br && sd.lit) bR = half * v.v[E - 1];
+    const T bRc = -half * tL;
+    o.v[0] += half * gL - sg * tL;
+    if (needEnd) {
+      o.v[n - 1] += aR;
+      o.v[n - 1] += T(kRef.d0[n - 1]) * bRc + T(kRef.d1[n - 1]) * bR;
+    }
+#pragma unroll
+    for (int mu = 0; mu < n - 1; ++mu) o.v[mu] += T(kRef.d0[mu]) * bRc + T(kRef.d1[mu]) * bR;
+  }
+}
+
+// o[j] = sum_p S[p][q] v[p], q = H n + j (coefficients of line_St_t)
+template <typename T, int TY, int SP, int H>
+__device__ __forceinline__ void half_St_t(const Tab<K, T>* __restrict__ t, const Line<T>& v, Half<T>& o) {
+  using B = FDB<SP, TY>;
+  const T* S = fd_S<T, SP>(t, TY);
+#pragma unroll
+  for (int j = 0; j < n; ++j) {
+    const int q = H * n + j;
+    T s = T(0);
+    if (q < B::QN) {
+#pragma unroll
+      for (int p = B::PLO; p < B::PHI; ++p) s += S[p * E + q] * v.v[p];
+    }
+    o.v[j] = s;
+  }
+}
+// o[j] = sum_q S[p][q] v[q], p = H n + j
+template <typename T, int TY, int SP, int H>
+__device__ __forceinline__ void half_S_t(const Tab<K, T>* __restrict__ t, const Line<T>& v, Half<T>& o) {
+  using B = FDB<SP, TY>;
+  const T* S = fd_S<T, SP>(t, TY);
+#pragma unroll
+  for (int j = 0; j < n; ++j) {
+    const int p = H * n + j;
+    T s = T(0);
+    if (p >= B::PLO && p < B::PHI) {
+#pragma unroll
+      for (int q = 0; q < B::QN; ++q) s += S[p * E + q] * v.v[q];
+    }
+    o.v[j] = s;
+  }
+}
+template <typename T, int SP, int H>
+__device__ __forceinline__ void half_St(const Tab<K, T>* __restrict__ t, int ty, const Line<T>& v, Half<T>& o) {
+  switch (ty) {
+    case 0: half_St_t<T, 0, SP, H>(t, v, o); break;
+    case 1: half_St_t<T, 1, SP, H>(t, v, o); break;
+    case 2: half_St_t<T, 2, SP, H>(t, v, o); break;
+    default: half_St_t<T, 3, SP, H>(t, v, o); break;
+  }
+}
+template <typename T, int SP, int H>
+__device__ __forceinline__ void half_S(const Tab<K, T>* __restrict__ t, int ty, const Line<T>& v, Half<T>& o) {
+  switch (ty) {
+    case 0: half_S_t<T, 0, SP, H>(t, v, o); break;
+    case 1: half_S_t<T, 1, SP, H>(t, v, o); break;
+    case 2: half_S_t<T, 2, SP, H>(t, v, o); break;
+    default: half_S_t<T, 3, SP, H>(t, v, o); break;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_half(T* s, int base, int stride, int H, const Half<T>& o) {
+#pragma unroll
+  for (int j = 0; j < n; ++j) s[base + (H * n + j) * stride] = o.v[j];
+}
+
+// last-direction (z) line of b, the cells of half H only
+template <typename T>
+__device__ __forceinline__ void read_lasthalf(const T* __restrict__ b, int N, const PatchPos& P, int l, int H,
+                                              Half<T>& v) {
+  const long long base = node_offset(N, P, l % E, l / E, 0) + (long long)H * N * N * NC;
+#pragma unroll
+  for (int j = 0; j < n; ++j) v.v[j] = b[base + j * (n * n)];
+}
+
+constexpr bool kSplitOK = (D == 3) && (TPP % 64 == 0);
+
+template <typename T, int MODE, bool PREFETCH, bool ZERO, int H>
+__device__ __forceinline__ void smooth_split_body(const Tab<K, T>* __restrict__ t, const PatchGrid& g,
+                                                  T scale, T inv_scale, T* __restrict__ x,
+                                                  const T* __restrict__ b, long long ndof, int pid,
+                                                  int lane, T* sm, int rhs) {
+  static_assert(MODE != 3, "the Full kernel is not split");
+  constexpr int SP = (MODE == 4) ? SP_CLAMPED : SP_DIR;
+  constexpr int OPM = (MODE == 4) ? 2 : MODE;
+  const bool active = pid < g.npatch;
+  T* A = sm;
+  T* B = A + TS;
+  T* ext = B + TS;
+  const long long roff = (long long)rhs * ndof;
+  T* xr = x + roff;
+  const T* br = b + roff;
+  const PatchPos P = patch_pos(g, active ? pid : 0);
+  const int tyx = P.ty[0], tyy = P.ty[1], tyz = P.ty[2];
+  // ends of this half's cell that lie on the patch boundary are needed only
+  // on the domain boundary (Dirichlet and clamped spaces)
+  const bool endx = (tyx & (H == 0 ? 1 : 2)) != 0;
+  const bool endy = (tyy & (H == 0 ? 1 : 2)) != 0;
+  const bool endz = (tyz & (H == 0 ? 1 : 2)) != 0;
+  Half<T> xh;  // this half of the thread's x-line of x
+  Half<T> bh;  // this half of the thread's z-line of b
+  if (PREFETCH && active) read_lasthalf<T>(br, g.N, P, lane, H, bh);
+  if constexpr (ZERO) {
+#pragma unroll
+    for (int j = 0; j < n; ++j) xh.v[j] = T(0);
+    if (active) {
+      // r = b: this half to A, then S_z^T over whole lines into B
+      if (!PREFETCH) read_lasthalf<T>(br, g.N, P, lane, H, bh);
+      int base, stride;
+      line_geom(2, lane, base, stride);
+      store_half(A, base, stride, H, bh);
+    }
+    __syncthreads();
+  } else {
+    const Sides<T> ysd = active ? yline_sides_global<T, OPM>(t, xr, g.N, P, lane % E, lane / E) : Sides<T>{};
+    // X0: a = M_x x, b = L_x x on this half -> A, B
+    if (active) {
+      // z-face traces, spread over both waves
+      for (int i = lane + H * TPP; i < 2 * NF; i += 2 * TPP) {
+        const int f = i % NF;
+        const int side = i / NF;
+        const int nb = (side == 0) ? P.lo[2] - 1 : P.lo[2] + 2;
+        T beta = T(0);
+        if (MODE == 1 && nb >= 0 && nb < g.N) {
+          const int a = f % E, bb = f / E;
+          const long long base = cell_index(g.N, P.lo[0] + a / n, P.lo[1] + bb / n, nb) * NC + a % n +
+                                 n * (bb % n);
+          const T tr = xr[base + (long long)((side == 0) ? K : 0) * n * n];
+          beta = (side == 0) ? -T(0.5) * tr : T(0.5) * tr;
+        }
+        ext[side * NF + f] = beta;
+      }
+      const int py = lane % E, pz = lane / E;
+      const long long row0 = xrow_offset(g.N, P, py, pz);
+      Line<T> xl;
+      read_xline<T>(xr, row0, xl);
+      const Sides<T> sd = xline_sides<T, OPM>(t, xr, g.N, P, row0);
+#pragma unroll
+      for (int j = 0; j < n; ++j) xh.v[j] = xl.v[H * n + j];
+      int base, stride;
+      line_geom(0, lane, base, stride);
+      Half<T> a, bb;
+      half_mass<T, H>(xl, a, endx);
+      half_sipg<T, H, false>(t, xl, sd, bb, endx);
+      store_half(A, base, stride, H, a);
+      store_half(B, base, stride, H, bb);
+    }
+    __syncthreads();
+    // Y: c = M_y b + L_y a -> B, d = M_y a -> A (after both waves have read)
+    Half<T> c, d;
+    int ybase = 0, ystride = 0;
+    if (active) {
+      const int px = lane % E, pz = lane / E;
+      line_geom(1, lane, ybase, ystride);
+      Line<T> a, bl;
+      load_line(A, ybase, ystride, a);
+      load_line(B, ybase, ystride, bl);
+      (void)px;
+      (void)pz;
+      half_mass<T, H>(bl, c, endy);
+      half_sipg<T, H, true>(t, a, ysd, c, endy);
+      half_mass<T, H>(a, d, endy);
+      // z-face traces contracted along x (16 rows, one per thread of wave 1)
+      if (H == 1 && lane < 2 * E) extz_mass_x_line<T, 1>(t, ext, lane);
+    }
+    __syncthreads();
+    if (active) {
+      store_half(B, ybase, ystride, H, c);
+      store_half(A, ybase, ystride, H, d);
+    }
+    __syncthreads();
+    // Z: y = M_z c + L_z d, r = b - scale y on this half -> A, then S_z^T
+    if (active) {
+      const int px = lane % E, py = lane / E;
+      int base, stride;
+      line_geom(2, lane, base, stride);
+      Line<T> cl, dl;
+      load_line(B, base, stride, cl);
+      load_line(A, base, stride, dl);
+      Sides<T> sd = zline_sides<T, 1>(t, ext, g.N, P, px, py);
+      sd.lit = (OPM == 2);
+      Half<T> y;
+      half_mass<T, H>(cl, y, endz);
+      half_sipg<T, H, true>(t, dl, sd, y, endz);
+      if (!PREFETCH) read_lasthalf<T>(br, g.N, P, lane, H, bh);
+#pragma unroll
+      for (int j = 0; j < n; ++j) bh.v[j] -= scale * y.v[j];
+    }
+    __syncthreads();
+    if (active) {
+      int base, stride;
+      line_geom(2, lane, base, stride);
+      store_half(A, base, stride, H, bh);
+    }
+    __syncthreads();
+  }
+  // S_z^T over the whole residual line -> B
+  if (active) {
+    int base, stride;
+    line_geom(2, lane, base, stride);
+    Line<T> r;
+    load_line(A, base, stride, r);
+    Half<T> o;
+    half_St<T, SP, H>(t, tyz, r, o);
+    store_half(B, base, stride, H, o);
+  }
+  __syncthreads();
+  // X1: S_x^T, B -> A
+  if (active) {
+    int base, stride;
+    line_geom(0, lane, base, stride);
+    Line<T> v;
+    load_line(B, base, stride, v);
+    Half<T> o;
+    half_St<T, SP, H>(t, tyx, v, o);
+    store_half(A, base, stride, H, o);
+  }
+  __syncthreads();
+  // Y1a: S_y^T and 1/(sum lambda), A -> B
+  if (active) {
+    const int qx = lane % E, qz = lane / E;
+    int base, stride;
+    line_geom(1, lane, base, stride);
+    const T* ly = fd_lam<T, SP>(t, tyy);
+    const T lt = fd_lam<T, SP>(t, tyx)[qx] + fd_lam<T, SP>(t, tyz)[qz];
+    Line<T> v;
+    load_line(A, base, stride, v);
+    Half<T> o;
+    half_St<T, SP, H>(t, tyy, v, o);
+#pragma unroll
+    for (int j = 0; j < n; ++j) o.v[j] = o.v[j] * (inv_scale * recip(ly[H * n + j] + lt));
+    store_half(B, base, stride, H, o);
+  }
+  __syncthreads();
+  // Y1b: S_y, B -> A
+  if (active) {
+    int base, stride;
+    line_geom(1, lane, base, stride);
+    Line<T> v;
+    load_line(B, base, stride, v);
+    Half<T> o;
+    half_S<T, SP, H>(t, tyy, v, o);
+    store_half(A, base, stride, H, o);
+  }
+  __syncthreads();
+  // Z1: S_z, A -> B
+  if (active) {
+    int base, stride;
+    line_geom(2, lane, base, stride);
+    Line<T> v;
+    load_line(A, base, stride, v);
+    Half<T> o;
+    half_S<T, SP, H>(t, tyz, v, o);
+    store_half(B, base, stride, H, o);
+  }
+  __syncthreads();
+  // X2: x += S_x delta on this half's cell row of the kept lines
+  if (active) {
+    const int py = lane % E, pz = lane / E;
+    const bool keep_line = ZERO || ((py > 0 || (tyy & 1)) && (py < E - 1 || (tyy & 2)) &&
+                                    (pz > 0 || (tyz & 1)) && (pz < E - 1 || (tyz & 2)));
+    if (keep_line) {
+      int base, stride;
+      line_geom(0, lane, base, stride);
+      Line<T> v;
+      load_line(B, base, stride, v);
+      Half<T> dl;
+      half_S<T, SP, H>(t, tyx, v, dl);
+      Half<T> nx;
+#pragma unroll
+      for (int j = 0; j < n; ++j) nx.v[j] = xh.v[j] + dl.v[j];
+      if (H == 0 && !(tyx & 1)) nx.v[0] = xh.v[0];
+      if (H == 1 && !(tyx & 2)) nx.v[n - 1] = xh.v[n - 1];
+      const long long row = xrow_offset(g.N, P, py, pz) + (long long)H * NC;
+#pragma unroll
+      for (int j = 0; j < n; ++j) xr[row + j] = nx.v[j];
+    }
+  }
+}
+
+template <typename T, int PPB, int MODE, bool PREFETCH, bool ZERO = false>
+__global__ void __launch_bounds__(2 * TPP * PPB)
+k_smooth_split(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale, T* __restrict__ x,
+               const T* __restrict__ b, long long ndof) {
+  constexpr int PP = smooth_pp<1>();
+  __shared__ T smem[PPB * PP];
+  const int w = (int)threadIdx.x / TPP;  // wave group: slot * 2 + half
+  const int ws = kSplitOK ? __builtin_amdgcn_readfirstlane(w) : w;
+  const int slot = ws / 2, h = ws % 2, lane = threadIdx.x % TPP;
+  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
+  if (h == 0)
+    smooth_split_body<T, MODE, PREFETCH, ZERO, 0>(t, g, scale, inv_scale, x, b, ndof, pid, lane,
+                                                  smem + slot * PP, blockIdx.y);
+  else
+    smooth_split_body<T, MODE, PREFETCH, ZERO, 1>(t, g, scale, inv_scale, x, b, ndof, pid, lane,
+                                                  smem + slot * PP, blockIdx.y);
+}
+
 // ------------------------------------------------- residual + restriction
 // bc = P^T (b - A x): the colour-0 patch of level l is the set of children of
 // one coarse cell, so its residual contracts with the stacked P^T per
@@ -1308,7 +1700,8 @@ hipError_t launch_mass(const void* tab, PatchGrid g, T scale, const T* x, T* y, 
                      (const Tab<K, T>*)tab, g, scale, x, y, ndof);
   return hipGetLastError();
 }
-// smoother shapes: bit 0 selects the workgroup shape, bit 1 the prefetch of b;
+// smoother shapes: bit 0 selects the workgroup shape, bit 1 the prefetch of b,
+// bit 2 two waves per patch (where kSplitOK; otherwise the same as bit 2 clear);
 // variant 0 / 1 / 2 / 3: Dirichlet consistent / Dirichlet with the paper's
 // residual / Full / clamped
 template <typename T, int V>
@@ -1316,8 +1709,35 @@ hipError_t launch_smooth(const void* tab, PatchGrid g, T scale, T inv_scale, int
                          const T* xin, T* xout, const T* b, int nrhs, long long ndof, hipStream_t s) {
   constexpr int PPB = Shape<(V & 1)>::PPB;
   constexpr bool PF = (V & 2) != 0;
+  constexpr bool SPLIT = (V & 4) != 0 && kSplitOK;
   dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
   const Tab<K, T>* tb = (const Tab<K, T>*)tab;
+  if constexpr (SPLIT) {
+    if (variant != 2) {
+      const dim3 block(2 * TPP * PPB);
+      if (zero) {
+        if (variant == 3)
+          hipLaunchKernelGGL((k_smooth_split<T, PPB, 4, false, true>), grid, block, 0, s, tb, g, scale,
+                             inv_scale, xout, b, ndof);
+        else if (variant == 1)
+          hipLaunchKernelGGL((k_smooth_split<T, PPB, 2, false, true>), grid, block, 0, s, tb, g, scale,
+                             inv_scale, xout, b, ndof);
+        else
+          hipLaunchKernelGGL((k_smooth_split<T, PPB, 1, false, true>), grid, block, 0, s, tb, g, scale,
+                             inv_scale, xout, b, ndof);
+      } else if (variant == 3) {
+        hipLaunchKernelGGL((k_smooth_split<T, PPB, 4, PF>), grid, block, 0, s, tb, g, scale, inv_scale,
+                           xout, b, ndof);
+      } else if (variant == 1) {
+        hipLaunchKernelGGL((k_smooth_split<T, PPB, 2, PF>), grid, block, 0, s, tb, g, scale, inv_scale,
+                           xout, b, ndof);
+      } else {
+        hipLaunchKernelGGL((k_smooth_split<T, PPB, 1, PF>), grid, block, 0, s, tb, g, scale, inv_scale,
+                           xout, b, ndof);
+      }
+      return hipGetLastError();
+    }
+  }
   if (zero) {  // x = 0, colour 0: the residual is b, no prefetch needed
     if (variant == 2)
       hipLaunchKernelGGL((k_smooth<T, PPB, 3, false, true>), grid, dim3(TPP * PPB), 0, s, tb, g,
@@ -1403,6 +1823,11 @@ KernelSet<T> make_set() {
   k.smooth[1] = &launch_smooth<T, 1>;
   k.smooth[2] = &launch_smooth<T, 2>;
   k.smooth[3] = &launch_smooth<T, 3>;
+  k.smooth[4] = &launch_smooth<T, 4>;
+  k.smooth[5] = &launch_smooth<T, 5>;
+  k.smooth[6] = &launch_smooth<T, 6>;
+  k.smooth[7] = &launch_smooth<T, 7>;
+  k.smooth_split = kSplitOK ? 1 : 0;
   k.restrict_residual = &launch_restrict<T>;
   k.prolongate_add = &launch_prolong<T>;
   k.coarse = &launch_coarse<T>;

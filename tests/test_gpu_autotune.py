@@ -1,4 +1,5 @@
-"""The autotuner's choices are all correct: every workgroup shape and patch
+"""The autotuner's choices are all correct: every workgroup shape (patches
+per workgroup, b prefetch, one or two waves per patch) and patch
 numbering it can pick is forced through its JSON cache and checked against
 the oracle; tuning writes the cache and a second call reads it back."""
 import itertools
@@ -31,7 +32,7 @@ def rel(a, b):
 
 def force_cache(path, dim, k, L, nrhs, shape, remap):
     """Cache entries forcing the FP64 apply (shape mod 2) and the FP64
-    smoother on every level (shape 0..3) to one choice."""
+    smoother on every level (shape 0..7) to one choice."""
     lines = []
     keys = [("apply", shape % 2)] + [(f"smooth/l{l}", shape) for l in range(1, L + 1)]
     for kern, sh in keys:
@@ -41,7 +42,7 @@ def force_cache(path, dim, k, L, nrhs, shape, remap):
 
 
 @pytest.mark.parametrize("dim,k,L", [(2, 2, 3), (2, 5, 2), (3, 1, 2), (3, 2, 2), (3, 3, 2), (3, 4, 1)])
-@pytest.mark.parametrize("shape,remap", list(itertools.product([0, 1, 2, 3], [0, 1])))
+@pytest.mark.parametrize("shape,remap", list(itertools.product(range(8), [0, 1])))
 def test_every_tunable_shape_matches_oracle(tmp_path, dim, k, L, shape, remap):
     note(f"tuned shape={shape} remap={remap} d={dim} k={k} L={L}")
     nrhs = 2
@@ -84,3 +85,36 @@ def test_tuning_writes_and_reads_cache(tmp_path):
     x, it, relres = prob.solve(B, rtol=1e-10)
     assert np.all(relres <= 1e-10) and np.all(it <= 15)
     prob.close()
+
+
+@pytest.mark.parametrize("dim,k,L", [(3, 3, 2), (3, 7, 1)])
+@pytest.mark.parametrize("variant", [0, 1, 3])
+@pytest.mark.parametrize("precision", [64, 32])
+def test_two_wave_shapes_are_bitwise_one_wave(tmp_path, dim, k, L, variant, precision):
+    """The two-waves-per-patch smoother computes every output with the
+    operations of the one-wave kernel: shapes 4..7 equal shapes 0..3 bit for
+    bit, for a smoothing step and for a V-cycle (colour 0 from zero)."""
+    note(f"two-wave bitwise d={dim} k={k} variant={variant} fp{precision}")
+    nrhs = 2
+    dt = torch.float64 if precision == 64 else torch.float32
+    X = inputs.uniform(61, (nrhs, 2 ** ((L + 1) * dim) * (k + 1) ** dim))
+    B = inputs.uniform(62, X.shape)
+    outs = {}
+    for shape in (0, 2, 4, 6):
+        prob = dgmg.Problem(dim, k, L, precision=precision, variant=variant, nrhs_max=nrhs)
+        cache = tmp_path / f"tune{shape}.json"
+        lines = []
+        for l in range(1, L + 1):
+            key = f"gfx950/d{dim}/k{k}/L{L}/nrhs{nrhs}/fp{precision}/smooth/l{l}"
+            lines.append(f'  "{key}": {{"shape": {shape}, "remap": 1, "us": 1.000}}')
+        cache.write_text("{\n" + ",\n".join(lines) + "\n}\n")
+        prob.autotune(nrhs=nrhs, cache=str(cache))
+        Xg = torch.from_numpy(X).to("cuda", dt)
+        prob.smooth(Xg, torch.from_numpy(B).to("cuda", dt))
+        V = prob.vcycle(torch.from_numpy(B).to("cuda", dt))
+        torch.cuda.synchronize()
+        outs[shape] = (Xg.cpu(), V.cpu())
+        prob.close()
+    for one, two in ((0, 4), (2, 6)):
+        assert torch.equal(outs[one][0], outs[two][0])
+        assert torch.equal(outs[one][1], outs[two][1])
