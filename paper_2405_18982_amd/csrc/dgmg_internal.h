@@ -8,7 +8,7 @@
 namespace dgmg {
 
 constexpr int kMaxDegree = 7;
-constexpr int kApplyShapes = 2;   // workgroup shapes of apply
+constexpr int kApplyShapes = 3;   // workgroup shapes of apply (2: face data in registers)
 constexpr int kSmoothShapes = 8;  // workgroup shape x prefetch of b x two waves per patch
 
 // Reference (h = 1, kappa = 1) data of Q_K on a two-cell patch that depends
@@ -55,6 +55,8 @@ struct KernelSet {
   // the smoother also whether b is prefetched)
   hipError_t (*apply[kApplyShapes])(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
                          long long ndof, hipStream_t s);
+  // 1 where apply shape 2 (face data in registers) differs from shape 0
+  int apply_rf;
   hipError_t (*mass)(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
                      long long ndof, hipStream_t s);
   // variant: DGMG_SMOOTH_* of the context.  The Dirichlet kernels update x in

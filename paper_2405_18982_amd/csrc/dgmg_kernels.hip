@@ -698,6 +698,191 @@ k_apply(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restri
   }
 }
 
+// ------------------------------------------- apply, face data in registers
+// Where the lines of a patch sit in one wave (3-D Q1 and Q3: TPP = 16 or 64
+// lanes), the face data of the y- and z-neighbours need not pass through LDS.
+// Lane l forms, for its y-line (px, pz) and for the z-face node (px, py) of
+// the same lane number, the couplings alpha, beta of the n face nodes of its
+// x-block from the neighbour's lines along the face normal, and contracts
+// them with the mass row of px in registers; the z-face values are then
+// contracted along y with the lanes of the same px in the y-block (lane
+// offsets E (nu - mu), cross-lane reads).  Every value is the expression of
+// gather_ext / ext_mx / extz_mass_x_line / ext_my in the same order, so the
+// result equals k_apply bit for bit; LDS holds only the two tiles (3-D Q3 in
+// FP64: 9 KB per patch instead of 13 KB, 16 patches per CU instead of 12).
+constexpr bool kApplyRF = (D == 3) && (TPP <= 64) && (64 % TPP == 0);
+
+// row[nu] = M[mu][nu] for a lane-dependent mu
+template <typename T>
+__device__ __forceinline__ void mass_row(int mu, T (&row)[n]) {
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) {
+    T v = T(kRef.M[nu]);
+#pragma unroll
+    for (int m = 1; m < n; ++m)
+      if (mu == m) v = T(kRef.M[m * n + nu]);
+    row[nu] = v;
+  }
+}
+
+// Couplings of the n face nodes nu of an x-block of a neighbour cell across
+// a y- or z-face (SIDE 0: the neighbour below, read at its far end; SIDE 1:
+// above, read at its near end); node nu, normal index j sits at
+// c[nu + j strideN].  a = sum_nu row[nu] alpha(nu), b = sum_nu row[nu] beta(nu).
+template <typename T, int SIDE>
+__device__ __forceinline__ void face_pair(const Tab<K, T>* __restrict__ t, const T* __restrict__ c,
+                                          int strideN, const T (&row)[n], T& a, T& b) {
+  const T half = T(0.5);
+  const T sg = t->sigma;
+  T al[n], be[n];
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) {
+    const T* r = c + nu;
+    const T tr = r[(SIDE == 0 ? K : 0) * strideN];
+    T g = T(0);
+#pragma unroll
+    for (int j = 0; j < n; ++j) g += (SIDE == 0 ? T(kRef.d1[j]) : T(kRef.d0[j])) * r[j * strideN];
+    al[nu] = (SIDE == 0) ? (half * g - sg * tr) : (-sg * tr - half * g);
+    be[nu] = (SIDE == 0) ? -half * tr : half * tr;
+  }
+  T sa = T(0), sb = T(0);
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) sa += row[nu] * al[nu];
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) sb += row[nu] * be[nu];
+  a = sa;
+  b = sb;
+}
+
+// sum_nu row[nu] v(lane + E (nu - mu)): the y-contraction of z-face values
+// held one per lane
+template <typename T>
+__device__ __forceinline__ T ycontract_lanes(const T (&row)[n], T v, int wl, int mu) {
+  T s = T(0);
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) s += row[nu] * __shfl(v, wl + E * (nu - mu), 64);
+  return s;
+}
+
+template <typename T, int PPB>
+__global__ void __launch_bounds__(TPP * PPB)
+k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
+           T* __restrict__ y, long long ndof) {
+  static_assert(kApplyRF && TPP * PPB <= 64, "one wave per workgroup");
+  constexpr int PP = 2 * TS;
+  __shared__ T smem[PPB * PP];
+  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  const int wl = threadIdx.x & 63;
+  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
+  const bool active = pid < g.npatch;
+  T* A = smem + slot * PP;
+  T* B = A + TS;
+  const long long roff = (long long)blockIdx.y * ndof;
+  const T* xr = x + roff;
+  T* yr = y + roff;
+  const int N = g.N;
+  const PatchPos P = patch_pos(g, active ? pid : 0);
+  // lane = px + E q: y-line (px, pz = q), z-face node (px, py = q)
+  const int px = lane % E, q = lane / E;
+  T rowx[n], rowy[n];
+  mass_row<T>(px % n, rowx);
+  mass_row<T>(q % n, rowy);
+  const bool ybl = (P.lo[1] == 0), ybr = (P.lo[1] + 1 == N - 1);
+  const bool zbl = (P.lo[2] == 0), zbr = (P.lo[2] + 1 == N - 1);
+  T ya0 = T(0), yb0 = T(0), ya1 = T(0), yb1 = T(0);
+  T za0 = T(0), zb0 = T(0), za1 = T(0), zb1 = T(0);
+  Line<T> xl;
+  if (active) {
+    const int cx = P.lo[0] + px / n;
+    {
+      const int cz = P.lo[2] + q / n;
+      const long long o = (long long)(n * n) * (q % n);
+      if (!ybl) face_pair<T, 0>(t, xr + cell_index(N, cx, P.lo[1] - 1, cz) * NC + o, n, rowx, ya0, yb0);
+      if (!ybr) face_pair<T, 1>(t, xr + cell_index(N, cx, P.lo[1] + 2, cz) * NC + o, n, rowx, ya1, yb1);
+    }
+    {
+      const int cy = P.lo[1] + q / n;
+      const long long o = (long long)n * (q % n);
+      if (!zbl) face_pair<T, 0>(t, xr + cell_index(N, cx, cy, P.lo[2] - 1) * NC + o, n * n, rowx, za0, zb0);
+      if (!zbr) face_pair<T, 1>(t, xr + cell_index(N, cx, cy, P.lo[2] + 2) * NC + o, n * n, rowx, za1, zb1);
+    }
+    // X0: a = M_x x -> A, b = L_x x -> B
+    const int py = lane % E, pz = lane / E;
+    const long long row0 = xrow_offset(N, P, py, pz);
+    read_xline<T>(xr, row0, xl);
+    const Sides<T> sd = xline_sides<T, 0>(t, xr, N, P, row0);
+    int base, stride;
+    line_geom(0, lane, base, stride);
+    Line<T> a, b;
+    line_mass<T>(t, xl, a);
+    line_sipg<T, false>(t, xl, sd, b);
+    store_line(A, base, stride, a);
+    store_line(B, base, stride, b);
+  }
+  __syncthreads();
+  // Y: c = M_y b + L_y a -> B, d = M_y a -> A
+  if (active) {
+    int base, stride;
+    line_geom(1, lane, base, stride);
+    Line<T> a, b, c, d;
+    load_line(A, base, stride, a);
+    load_line(B, base, stride, b);
+    Sides<T> sd;
+    sd.bl = ybl;
+    sd.br = ybr;
+    sd.aL = ya0;
+    sd.bL = yb0;
+    sd.aR = ya1;
+    sd.bR = yb1;
+    sd.lit = false;
+    line_mass<T>(t, b, c);
+    line_sipg<T, true>(t, a, sd, c);
+    line_mass<T>(t, a, d);
+    store_line(B, base, stride, c);
+    store_line(A, base, stride, d);
+  }
+  // z-face values contracted along y (all lanes of a patch take part)
+  const int muy = q % n;
+  const T zaL = ycontract_lanes<T>(rowy, za0, wl, muy);
+  const T zbL = ycontract_lanes<T>(rowy, zb0, wl, muy);
+  const T zaR = ycontract_lanes<T>(rowy, za1, wl, muy);
+  const T zbR = ycontract_lanes<T>(rowy, zb1, wl, muy);
+  __syncthreads();
+  // Z: y = M_z c + L_z d
+  if (active) {
+    int base, stride;
+    line_geom(2, lane, base, stride);
+    Line<T> c, d, o;
+    load_line(B, base, stride, c);
+    load_line(A, base, stride, d);
+    Sides<T> sd;
+    sd.bl = zbl;
+    sd.br = zbr;
+    sd.aL = zbl ? T(0) : zaL;
+    sd.bL = zbl ? T(0) : zbL;
+    sd.aR = zbr ? T(0) : zaR;
+    sd.bR = zbr ? T(0) : zbR;
+    sd.lit = false;
+    line_mass<T>(t, c, o);
+    line_sipg<T, true>(t, d, sd, o);
+#pragma unroll
+    for (int p = 0; p < E; ++p) A[base + p * stride] = scale * o.v[p];
+  }
+  __syncthreads();
+  // X2: contiguous row stores
+  if (active) {
+    const int py = lane % E, pz = lane / E;
+    int base, stride;
+    line_geom(0, lane, base, stride);
+    const long long row0 = xrow_offset(N, P, py, pz);
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      yr[row0 + a] = A[base + a];
+      yr[row0 + NC + a] = A[base + n + a];
+    }
+  }
+}
+
 // ----------------------------------------------------------------- mass
 template <typename T, int PPB>
 __global__ void __launch_bounds__(TPP * PPB)
@@ -1691,6 +1876,20 @@ hipError_t launch_apply(const void* tab, PatchGrid g, T scale, const T* x, T* y,
                      (const Tab<K, T>*)tab, g, scale, x, y, ndof);
   return hipGetLastError();
 }
+// shape 2: face data in registers where kApplyRF (otherwise shape 0)
+template <typename T>
+hipError_t launch_apply_rf(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
+                           long long ndof, hipStream_t s) {
+  if constexpr (!kApplyRF) {
+    return launch_apply<T, 0>(tab, g, scale, x, y, nrhs, ndof, s);
+  } else {
+    constexpr int PPB = PPB_DEFAULT;
+    dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
+    hipLaunchKernelGGL((k_apply_rf<T, PPB>), grid, dim3(TPP * PPB), 0, s,
+                       (const Tab<K, T>*)tab, g, scale, x, y, ndof);
+    return hipGetLastError();
+  }
+}
 template <typename T>
 hipError_t launch_mass(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
                        long long ndof, hipStream_t s) {
@@ -1818,6 +2017,8 @@ KernelSet<T> make_set() {
   KernelSet<T> k;
   k.apply[0] = &launch_apply<T, 0>;
   k.apply[1] = &launch_apply<T, 1>;
+  k.apply[2] = &launch_apply_rf<T>;
+  k.apply_rf = kApplyRF ? 1 : 0;
   k.mass = &launch_mass<T>;
   k.smooth[0] = &launch_smooth<T, 0>;
   k.smooth[1] = &launch_smooth<T, 1>;

@@ -31,10 +31,10 @@ def rel(a, b):
 
 
 def force_cache(path, dim, k, L, nrhs, shape, remap):
-    """Cache entries forcing the FP64 apply (shape mod 2) and the FP64
+    """Cache entries forcing the FP64 apply (shape mod 3) and the FP64
     smoother on every level (shape 0..7) to one choice."""
     lines = []
-    keys = [("apply", shape % 2)] + [(f"smooth/l{l}", shape) for l in range(1, L + 1)]
+    keys = [("apply", shape % 3)] + [(f"smooth/l{l}", shape) for l in range(1, L + 1)]
     for kern, sh in keys:
         key = f"gfx950/d{dim}/k{k}/L{L}/nrhs{nrhs}/fp64/{kern}"
         lines.append(f'  "{key}": {{"shape": {sh}, "remap": {remap}, "us": 1.000}}')
@@ -118,3 +118,26 @@ def test_two_wave_shapes_are_bitwise_one_wave(tmp_path, dim, k, L, variant, prec
     for one, two in ((0, 4), (2, 6)):
         assert torch.equal(outs[one][0], outs[two][0])
         assert torch.equal(outs[one][1], outs[two][1])
+
+
+@pytest.mark.parametrize("dim,k,L", [(3, 1, 3), (3, 3, 2), (3, 3, 1), (3, 2, 2)])
+def test_register_face_apply_is_bitwise_lds_apply(tmp_path, dim, k, L):
+    """Apply shape 2 (neighbour face data contracted in registers and across
+    lanes instead of through LDS; 3-D Q1 and Q3) evaluates every output with
+    the operations of shape 0: equal bit for bit, on every right-hand side."""
+    note(f"register-face apply bitwise d={dim} k={k} L={L}")
+    nrhs = 3
+    X = inputs.uniform(71, (nrhs, 2 ** ((L + 1) * dim) * (k + 1) ** dim))
+    outs = {}
+    for shape in (0, 2):
+        prob = dgmg.Problem(dim, k, L, nrhs_max=nrhs)
+        cache = tmp_path / f"tune{shape}.json"
+        key = f"gfx950/d{dim}/k{k}/L{L}/nrhs{nrhs}/fp64/apply"
+        cache.write_text("{\n" + f'  "{key}": {{"shape": {shape}, "remap": 1, "us": 1.000}}' + "\n}\n")
+        prob.autotune(nrhs=nrhs, cache=str(cache))
+        outs[shape] = prob.apply(torch.from_numpy(X).to("cuda", torch.float64)).cpu()
+        prob.close()
+    assert torch.equal(outs[0], outs[2])
+    A = kron_operator(dim, k, 2 ** (L + 1), inputs.sigma_of(k))
+    for j in range(nrhs):
+        assert rel(outs[2][j].numpy(), A @ X[j]) <= 1e-12
