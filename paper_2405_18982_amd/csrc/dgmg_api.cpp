@@ -135,9 +135,10 @@ struct dgmg_ctx {
   // the caller's stream.  Captured on the library's own stream (default
   // priority); invalidated when kappa changes.
   bool use_graph = true;
-  // levels 1 and 0 of the V-cycle in one launch where the kernels allow it
-  // (DGMG_FUSE_BOTTOM=0 at set-up turns it off, to measure its effect)
-  bool fuse_bottom = true;
+  // levels 1 and 0 of the V-cycle in one launch where the kernels allow it,
+  // with two waves per patch where they allow that (DGMG_FUSE_BOTTOM at
+  // set-up: 0 separate launches, 1 one wave per patch; to measure the effect)
+  int fuse_bottom = 2;
   // workgroup shape and XCD-aware numbering of the tuned kernels, per
   // precision (0: FP64, 1: FP32); set by dgmg_autotune
   struct Tuning {
@@ -418,7 +419,8 @@ dgmg_status vcycle_T(dgmg_ctx* c, const T* bL, T* xL, int nrhs) {
   }
   if (fuse) {
     const double s1 = level_scale(c, 1);
-    HIPCHK(c, kset<T>(c).bottom(tab_of<T>(c), c->variant, (T)s1, (T)(1.0 / s1),
+    const int split = (c->fuse_bottom >= 2 && kset<T>(c).bottom_split) ? 1 : 0;
+    HIPCHK(c, kset<T>(c).bottom(tab_of<T>(c), c->variant, split, (T)s1, (T)(1.0 / s1),
                                 (T)(1.0 / level_scale(c, 0)), X(1), B(1), lvb<T>(c->lv[0]),
                                 X(0), nrhs, c->lv[1].ndof, c->lv[0].ndof, c->stream));
   } else {
@@ -543,7 +545,7 @@ DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int sm
   c->variant = smoother_variant;
   {
     const char* e = std::getenv("DGMG_FUSE_BOTTOM");
-    c->fuse_bottom = !(e && e[0] == '0');
+    c->fuse_bottom = (e && e[0] == '0') ? 0 : (e && e[0] == '1') ? 1 : 2;
   }
   c->nrhs_max = nrhs_max;
   c->stream = (hipStream_t)hip_stream;

@@ -79,9 +79,11 @@ struct KernelSet {
   // levels 1 and 0 of the V-cycle in one launch (pre-smoothing from zero,
   // restriction, coarse solve, prolongation, post-smoothing); null where the
   // level-1 patches of a colour do not fit one workgroup
-  hipError_t (*bottom)(const void* tab, int variant, T scale1, T inv_scale1, T inv_scale0, T* x1,
-                       const T* b1, T* b0, T* x0, int nrhs, long long ndof1, long long ndof0,
+  // (split: two waves per patch in the smoothing stages, where bottom_split)
+  hipError_t (*bottom)(const void* tab, int variant, int split, T scale1, T inv_scale1, T inv_scale0,
+                       T* x1, const T* b1, T* b0, T* x0, int nrhs, long long ndof1, long long ndof0,
                        hipStream_t s);
+  int bottom_split;
 };
 
 // Registration entry of one kernel translation unit.

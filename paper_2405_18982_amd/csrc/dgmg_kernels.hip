@@ -1857,6 +1857,54 @@ k_bottom(const Tab<K, T>* __restrict__ t, BottomArgs<T> a) {
   }
 }
 
+// The same with two waves per patch in the smoothing stages (where kSplitOK
+// and 2^D two-wave slots fit one workgroup: 3-D Q3): waves 2s and 2s + 1 form
+// patch slot s, and the transfer and coarse stages run on the even waves while
+// the odd ones meet the barriers only.  The split smoothing body gives every
+// output bit for bit as the one-wave body.
+constexpr bool kBottomSplitOK = kSplitOK && 2 * TPP * kBottomSlots <= 1024;
+
+template <typename T, int MODE, bool ZERO>
+__device__ __forceinline__ void bottom_smooth_half(const Tab<K, T>* __restrict__ t, int colour,
+                                                   const BottomArgs<T>& a, int slot, int h, int lane,
+                                                   T* sm, int rhs) {
+  if (h == 0)
+    smooth_split_body<T, MODE, false, ZERO, 0>(t, level1_colour(colour), a.scale1, a.inv_scale1, a.x1,
+                                               a.b1, a.ndof1, slot, lane, sm, rhs);
+  else
+    smooth_split_body<T, MODE, false, ZERO, 1>(t, level1_colour(colour), a.scale1, a.inv_scale1, a.x1,
+                                               a.b1, a.ndof1, slot, lane, sm, rhs);
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(2 * TPP * kBottomSlots)
+k_bottom_split(const Tab<K, T>* __restrict__ t, BottomArgs<T> a) {
+  static_assert(kBottomSplitOK, "two-wave slots must fit one workgroup");
+  __shared__ T smem[kBottomSlots * kBottomPP];
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x / TPP);
+  const int slot = w / 2, h = w % 2, lane = threadIdx.x % TPP;
+  const int tslot = h == 0 ? slot : kBottomSlots;  // one-wave stages: odd waves hold no patch
+  T* sm = smem + slot * kBottomPP;
+  const int rhs = blockIdx.y;
+  constexpr int NCOL = 1 << D;
+  bottom_smooth_half<T, MODE, true>(t, 0, a, slot, h, lane, sm, rhs);
+  __syncthreads();
+  for (int c = 1; c < NCOL; ++c) {
+    bottom_smooth_half<T, MODE, false>(t, c, a, slot, h, lane, sm, rhs);
+    __syncthreads();
+  }
+  restrict_body<T>(t, level1_colour(0), a.scale1, a.x1, a.b1, a.b0, a.ndof1, a.ndof0, tslot, lane, sm, rhs);
+  __syncthreads();
+  coarse_body<T>(t, a.scale0_inv, a.b0, a.x0, a.ndof0, lane, sm, rhs, slot == 0 && h == 0);
+  __syncthreads();
+  prolong_body<T>(level1_colour(0), a.x0, a.x1, a.ndof1, a.ndof0, tslot, lane, sm, rhs);
+  __syncthreads();
+  for (int c = NCOL - 1; c >= 0; --c) {
+    bottom_smooth_half<T, MODE, false>(t, c, a, slot, h, lane, sm, rhs);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ launchers
 // Workgroup shapes the autotuner chooses between: PPB_DEFAULT patches per
 // workgroup (variant 0) or twice as many (variant 1) while the workgroup stays
@@ -1993,10 +2041,11 @@ hipError_t launch_coarse(const void* tab, T inv_scale, const T* b, T* x, int nrh
   return hipGetLastError();
 }
 
-// variant 0 / 1 / 3 (in-place smoothers); the Full kernel is not fused
+// variant 0 / 1 / 3 (in-place smoothers); the Full kernel is not fused.
+// split: two waves per patch in the smoothing stages where kBottomSplitOK.
 template <typename T>
-hipError_t launch_bottom(const void* tab, int variant, T scale1, T inv_scale1, T inv_scale0, T* x1,
-                         const T* b1, T* b0, T* x0, int nrhs, long long ndof1, long long ndof0,
+hipError_t launch_bottom(const void* tab, int variant, int split, T scale1, T inv_scale1, T inv_scale0,
+                         T* x1, const T* b1, T* b0, T* x0, int nrhs, long long ndof1, long long ndof0,
                          hipStream_t s) {
   if constexpr (!bottom_fits<T>()) {
     return hipErrorInvalidConfiguration;
@@ -2004,6 +2053,16 @@ hipError_t launch_bottom(const void* tab, int variant, T scale1, T inv_scale1, T
     const BottomArgs<T> a{scale1, inv_scale1, inv_scale0, x1, b1, b0, x0, ndof1, ndof0};
     const Tab<K, T>* tb = (const Tab<K, T>*)tab;
     const dim3 grid(1, nrhs), block(TPP * kBottomSlots);
+    if constexpr (kBottomSplitOK) {
+      if (split) {
+        const dim3 block2(2 * TPP * kBottomSlots);
+        if (variant == 0) hipLaunchKernelGGL((k_bottom_split<T, 1>), grid, block2, 0, s, tb, a);
+        else if (variant == 1) hipLaunchKernelGGL((k_bottom_split<T, 2>), grid, block2, 0, s, tb, a);
+        else if (variant == 3) hipLaunchKernelGGL((k_bottom_split<T, 4>), grid, block2, 0, s, tb, a);
+        else return hipErrorInvalidValue;
+        return hipGetLastError();
+      }
+    }
     if (variant == 0) hipLaunchKernelGGL((k_bottom<T, 1>), grid, block, 0, s, tb, a);
     else if (variant == 1) hipLaunchKernelGGL((k_bottom<T, 2>), grid, block, 0, s, tb, a);
     else if (variant == 3) hipLaunchKernelGGL((k_bottom<T, 4>), grid, block, 0, s, tb, a);
@@ -2033,6 +2092,7 @@ KernelSet<T> make_set() {
   k.prolongate_add = &launch_prolong<T>;
   k.coarse = &launch_coarse<T>;
   k.bottom = bottom_fits<T>() ? &launch_bottom<T> : nullptr;
+  k.bottom_split = (bottom_fits<T>() && kBottomSplitOK) ? 1 : 0;
   return k;
 }
 

@@ -329,12 +329,12 @@ def test_graph_replays_equal_eager(precision):
     (2, 2, 1, 64, 0), (2, 5, 3, 64, 0), (3, 1, 2, 64, 0), (3, 2, 1, 64, 0), (3, 3, 3, 64, 0),
     (3, 3, 2, 32, 0), (3, 4, 2, 32, 0), (3, 3, 2, 64, 1), (3, 3, 2, 64, 3), (3, 4, 1, 64, 0)])
 def test_fused_vcycle_bottom_equals_separate_kernels(monkeypatch, dim, k, L, precision, variant):
-    """Levels 1 and 0 in one launch give bitwise the V-cycle of the separate
-    kernels (where the kernels allow the fusion; elsewhere both paths are the
-    separate kernels)."""
+    """Levels 1 and 0 in one launch, with one or two waves per patch, give
+    bitwise the V-cycle of the separate kernels (where the kernels allow the
+    fusion; elsewhere the paths fall back to the separate kernels)."""
     note(f"fused bottom d={dim} k={k} L={L} fp{precision} variant={variant}")
     outs = {}
-    for fuse in ("1", "0"):
+    for fuse in ("2", "1", "0"):
         monkeypatch.setenv("DGMG_FUSE_BOTTOM", fuse)
         prob = dgmg.Problem(dim, k, L, precision=precision, variant=variant, nrhs_max=2)
         B = inputs.uniform(33, (2, prob.ndofs()))
@@ -345,5 +345,5 @@ def test_fused_vcycle_bottom_equals_separate_kernels(monkeypatch, dim, k, L, pre
         outs[fuse] = res
         prob.close()
     torch.cuda.synchronize()
-    for a, b in zip(outs["1"], outs["0"]):
-        assert torch.equal(a, b)
+    for a, b, c in zip(outs["2"], outs["1"], outs["0"]):
+        assert torch.equal(a, c) and torch.equal(b, c)
