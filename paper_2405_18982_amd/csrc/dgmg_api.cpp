@@ -8,6 +8,7 @@
 //   level l = 1 .. L: prolongation + add, smooth (colours reversed)
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -131,6 +132,15 @@ struct dgmg_ctx {
   int* active = nullptr;
   double* hbuf = nullptr;  // pinned host mirror of scalars
   int* hact = nullptr;
+  // CG convergence decided on the device: norms of b (device, uploaded from
+  // the pinned hnb once per solve), the update kernel's record (pinned host
+  // memory, 4 doubles per right-hand side; rec_dev is its device address) and
+  // the event the host waits on by polling
+  double* nb = nullptr;
+  double* hnb = nullptr;
+  double* rec = nullptr;
+  double* rec_dev = nullptr;
+  hipEvent_t ev_check = nullptr;
   // V-cycle of the CG (r -> z) captured as a HIP graph, per nrhs; replayed on
   // the caller's stream.  Captured on the library's own stream (default
   // priority); invalidated when kappa changes.
@@ -453,6 +463,18 @@ void drop_graphs(dgmg_ctx* c) {
     }
 }
 
+// Wait for an event by polling it (no sleep on the stream: the host sees the
+// completion within microseconds and launches the next work at once).
+dgmg_status poll_event(dgmg_ctx* c, hipEvent_t ev) {
+  for (;;) {
+    const hipError_t e = hipEventQuery(ev);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) return fail(c, DGMG_ERR_HIP, std::string("event: ") + hipGetErrorString(e));
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return DGMG_OK;
+}
+
 // z = V(r) for the CG: replay (capturing on first use) the graph of the
 // V-cycle on the CG workspace for this nrhs.
 dgmg_status precondition_cg(dgmg_ctx* c, int nrhs) {
@@ -566,9 +588,14 @@ DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int sm
   if (e == hipSuccess) c->partial = dalloc<double>((long long)dgmg::kRedBlocks * nrhs_max, e);
   if (e == hipSuccess) c->partial2 = dalloc<double>((long long)dgmg::kRedBlocks * nrhs_max, e);
   if (e == hipSuccess) c->active = dalloc<int>(nrhs_max, e);
+  if (e == hipSuccess) c->nb = dalloc<double>(nrhs_max, e);
   if (e != hipSuccess) return fail(c, DGMG_ERR_ALLOC, "workspace allocation failed");
   HIPCHK(c, hipHostMalloc((void**)&c->hbuf, sizeof(double) * kNumScal * nrhs_max));
   HIPCHK(c, hipHostMalloc((void**)&c->hact, sizeof(int) * nrhs_max));
+  HIPCHK(c, hipHostMalloc((void**)&c->hnb, sizeof(double) * nrhs_max));
+  HIPCHK(c, hipHostMalloc((void**)&c->rec, sizeof(double) * 4 * nrhs_max));
+  HIPCHK(c, hipHostGetDevicePointer((void**)&c->rec_dev, c->rec, 0));
+  HIPCHK(c, hipEventCreateWithFlags(&c->ev_check, hipEventDisableTiming));
   c->ready = true;
   if (vcycle_precision == DGMG_FP64) RET(ensure_levels<double>(c, c->L - 1));
   else RET(ensure_levels<float>(c, c->L));
@@ -754,6 +781,8 @@ DGMG_API dgmg_status dgmg_pcg_solve(dgmg_ctx* c, const double* b, double* x, int
     any = any || c->hact[j];
   }
   if (!any) return DGMG_OK;
+  for (int j = 0; j < nrhs; ++j) c->hnb[j] = nb[j];
+  HIPCHK(c, hipMemcpyAsync(c->nb, c->hnb, sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->active, c->hact, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
   RET(precondition_cg(c, nrhs));
   HIPCHK(c, dgmg::blas_dot2(c->r, c->z, nullptr, nullptr, n, nrhs, c->partial, nullptr, rzb[0],
@@ -764,30 +793,35 @@ DGMG_API dgmg_status dgmg_pcg_solve(dgmg_ctx* c, const double* b, double* x, int
     double* rz_old = rzb[(it - 1) & 1];
     double* rz_new = rzb[it & 1];
     RET(op_apply<double>(c, c->L, c->p, c->q, nrhs));
-    HIPCHK(c, dgmg::blas_dot2(c->p, c->q, nullptr, nullptr, n, nrhs, c->partial, nullptr, pq,
+    // p^T q stays as first-stage partial sums; the update finishes it
+    HIPCHK(c, dgmg::blas_dot2(c->p, c->q, nullptr, nullptr, n, nrhs, c->partial, nullptr, nullptr,
                               nullptr, s));
-    HIPCHK(c, dgmg::blas_update_xr(x, c->r, c->p, c->q, rz_old, pq, c->active, n, nrhs, alpha,
-                                   c->partial, rr, s));
-    HIPCHK(c, hipMemcpyAsync(c->hbuf + S_RR * R, rr, sizeof(double) * 2 * R, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    // the check kernel decides convergence on the device (active mask for the
+    // next iteration) and records (|r|^2, p^T q, relres, active) in pinned
+    // host memory; the host polls the event instead of sleeping on the stream
+    HIPCHK(c, dgmg::blas_update_xr(x, c->r, c->p, c->q, rz_old, c->partial, pq, c->active, n, nrhs,
+                                   alpha, c->partial2, s));
+    HIPCHK(c, dgmg::blas_cg_check(c->partial2, n, nrhs, rr, pq, c->nb, rtol, c->active, c->rec_dev, s));
+    HIPCHK(c, hipEventRecord(c->ev_check, s));
+    RET(poll_event(c, c->ev_check));
     any = false;
     for (int j = 0; j < nrhs; ++j) {
       if (!c->hact[j]) continue;
-      const double p2 = c->hbuf[S_PQ * R + j], r2 = c->hbuf[S_RR * R + j];
+      const double r2 = c->rec[4 * j + 0], p2 = c->rec[4 * j + 1];
       if (!(p2 > 0) || !std::isfinite(p2) || !std::isfinite(r2))
         return fail(c, DGMG_ERR_BREAKDOWN, "CG breakdown: p^T A p <= 0 or non-finite scalar");
       iters[j] = it;
-      relres[j] = std::sqrt(r2) / nb[j];
-      if (relres[j] <= rtol) c->hact[j] = 0;
+      relres[j] = c->rec[4 * j + 2];
+      c->hact[j] = c->rec[4 * j + 3] != 0.0 ? 1 : 0;
       any = any || c->hact[j];
     }
     if (!any) { status = DGMG_OK; break; }
-    HIPCHK(c, hipMemcpyAsync(c->active, c->hact, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
     RET(precondition_cg(c, nrhs));
+    // r^T z (and z^T q) stay as partial sums; the update of p finishes them
     HIPCHK(c, dgmg::blas_dot2(c->r, c->z, flexible ? c->z : nullptr, flexible ? c->q : nullptr, n,
-                              nrhs, c->partial, c->partial2, rz_new, zq, s));
-    HIPCHK(c, dgmg::blas_update_p(c->p, c->z, rz_new, rz_old, zq, alpha, c->active, flexible, n,
-                                  nrhs, s));
+                              nrhs, c->partial, c->partial2, nullptr, nullptr, s));
+    HIPCHK(c, dgmg::blas_update_p(c->p, c->z, c->partial, c->partial2, rz_new, zq, rz_old, alpha,
+                                  c->active, flexible, n, nrhs, s));
   }
   HIPCHK(c, hipStreamSynchronize(s));
   if (status != DGMG_OK) c->err = "maximum number of iterations reached";
@@ -1178,9 +1212,13 @@ DGMG_API dgmg_status dgmg_destroy(dgmg_ctx* c) {
   hipFree(c->partial);
   hipFree(c->partial2);
   hipFree(c->active);
+  hipFree(c->nb);
   free_gmres(c);
   if (c->hbuf) hipHostFree(c->hbuf);
   if (c->hact) hipHostFree(c->hact);
+  if (c->hnb) hipHostFree(c->hnb);
+  if (c->rec) hipHostFree(c->rec);
+  if (c->ev_check) hipEventDestroy(c->ev_check);
   delete c;
   return DGMG_OK;
 }

@@ -9,18 +9,28 @@ namespace dgmg {
 constexpr int kRedBlocks = 1024;
 
 // out[r] = a_r . b_r (and out2[r] = c_r . d_r when c != nullptr), vectors
-// [nrhs][n]; deterministic for given (n, nrhs).
+// [nrhs][n]; deterministic for given (n, nrhs).  out == nullptr (out2 ==
+// nullptr): only the first-stage partial sums, which the consuming kernel
+// finishes itself (the same value bit for bit).
 hipError_t blas_dot2(const double* a, const double* b, const double* c, const double* d,
                      long long n, int nrhs, double* partial, double* partial2, double* out,
                      double* out2, hipStream_t s);
-// CG update with alpha = rz / pq per active right-hand side; rr = |r|^2.
+// CG update x += alpha p, r -= alpha q, alpha = rz / pq per active right-hand
+// side, with p^T q finished from the partial sums pq_part of blas_dot2 (and
+// stored to pq); partial: first-stage sums of |r|^2 (must not alias pq_part).
 hipError_t blas_update_xr(double* x, double* r, const double* p, const double* q, const double* rz,
-                          const double* pq, const int* active, long long n, int nrhs,
-                          double* alpha, double* partial, double* rr, hipStream_t s);
-// p = z + beta p per active right-hand side.
-hipError_t blas_update_p(double* p, const double* z, const double* rz_new, const double* rz_old,
-                         const double* zq, const double* alpha, const int* active, int flexible,
-                         long long n, int nrhs, hipStream_t s);
+                          const double* pq_part, double* pq, const int* active, long long n,
+                          int nrhs, double* alpha, double* partial, hipStream_t s);
+// rr = |r|^2 from rr_part; active &&= sqrt(rr) / nb > rtol; rec (device
+// address of host-visible memory, 4 doubles per right-hand side) =
+// (rr, pq, sqrt(rr) / nb, active).
+hipError_t blas_cg_check(const double* rr_part, long long n, int nrhs, double* rr, const double* pq,
+                         const double* nb, double rtol, int* active, double* rec, hipStream_t s);
+// p = z + beta p per active right-hand side, rz_new (and zq) finished from
+// the partial sums of blas_dot2 and stored.
+hipError_t blas_update_p(double* p, const double* z, const double* rz_part, const double* zq_part,
+                         double* rz_new, double* zq, const double* rz_old, const double* alpha,
+                         const int* active, int flexible, long long n, int nrhs, hipStream_t s);
 // out[i] = V_i . w for the m vectors V_i = V + i n (partial: m * kRedBlocks).
 hipError_t blas_multi_dot(const double* V, const double* w, long long n, int m, double* partial,
                           double* out, hipStream_t s);

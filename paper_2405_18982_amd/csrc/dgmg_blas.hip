@@ -48,29 +48,47 @@ k_dot2(const double* __restrict__ a, const double* __restrict__ b, const double*
   }
 }
 
+// sum_blk partial[blk] over nblk first-stage partial sums in a fixed order
+// (every thread of the block gets the result): the second stage of every
+// reduction, so a sum formed here equals the one k_finalize writes, bit for
+// bit, in whichever block or kernel it is formed
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partial, int nblk,
+                                               double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kRedThreads) s += partial[i];
+  return block_sum(s, sh);
+}
+
 // out[r] = sum_blk partial[r][blk] in a fixed order
 __global__ void __launch_bounds__(kRedThreads)
 k_finalize(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
   __shared__ double sh[kRedThreads];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += kRedThreads) s += partial[blockIdx.x * nblk + i];
-  const double r = block_sum(s, sh);
+  const double r = sum_partials(partial + blockIdx.x * nblk, nblk, sh);
   if (threadIdx.x == 0) out[blockIdx.x] = r;
 }
 
 // x += alpha p, r -= alpha q with alpha = rz/pq for active right-hand sides;
-// partial sums of |r|^2.
+// partial sums of |r|^2.  p^T q comes as the nblk first-stage partial sums of
+// the preceding dot product (pq_part); every block finishes that sum itself
+// (same value in every block) instead of waiting for another launch, and
+// block 0 stores it and alpha.
 __global__ void __launch_bounds__(kRedThreads)
 k_update_xr(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
             const double* __restrict__ q, const double* __restrict__ rz,
-            const double* __restrict__ pq, const int* __restrict__ active, long long n,
-            double* __restrict__ alpha_out, double* __restrict__ partial) {
+            const double* __restrict__ pq_part, int nblk, double* __restrict__ pq_out,
+            const int* __restrict__ active, long long n, double* __restrict__ alpha_out,
+            double* __restrict__ partial) {
   __shared__ double sh[kRedThreads];
   const int rhs = blockIdx.y;
   const long long off = (long long)rhs * n;
   const bool act = active[rhs] != 0;
-  const double alpha = act ? rz[rhs] / pq[rhs] : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) alpha_out[rhs] = alpha;
+  const double pq = sum_partials(pq_part + rhs * nblk, nblk, sh);
+  __syncthreads();
+  const double alpha = act ? rz[rhs] / pq : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    alpha_out[rhs] = alpha;
+    pq_out[rhs] = pq;
+  }
   double s = 0.0;
   const long long stride = (long long)gridDim.x * kRedThreads;
   for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
@@ -86,17 +104,56 @@ k_update_xr(double* __restrict__ x, double* __restrict__ r, const double* __rest
   if (threadIdx.x == 0) partial[rhs * gridDim.x + blockIdx.x] = red;
 }
 
-// p = z + beta p for active right-hand sides; beta = rz_new/rz_old (standard)
-// or -alpha zq / rz_old (flexible: z^T (r_new - r_old) / rz_old).
+// Convergence check after the CG update, one block per right-hand side:
+// rr = |r|^2 from the update's partial sums; for an active right-hand side
+// rel = sqrt(rr) / nb, which stays active while rel > rtol.  The record
+// rec[4 rhs ..] = (rr, p^T q, rel, active) goes to host-visible memory, the
+// mask to `active` for the kernels of the next iteration.
 __global__ void __launch_bounds__(kRedThreads)
-k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ rz_new,
-           const double* __restrict__ rz_old, const double* __restrict__ zq,
+k_cg_check(const double* __restrict__ rr_part, int nblk, double* __restrict__ rr_out,
+           const double* __restrict__ pq, const double* __restrict__ nb, double rtol,
+           int* __restrict__ active, double* __restrict__ rec) {
+  __shared__ double sh[kRedThreads];
+  const int rhs = blockIdx.x;
+  const double r2 = sum_partials(rr_part + rhs * nblk, nblk, sh);
+  if (threadIdx.x == 0) {
+    rr_out[rhs] = r2;
+    const bool act = active[rhs] != 0;
+    const double rel = sqrt(r2) / nb[rhs];
+    const int still = (act && rel > rtol) ? 1 : 0;
+    active[rhs] = still;
+    rec[4 * rhs + 0] = r2;
+    rec[4 * rhs + 1] = pq[rhs];
+    rec[4 * rhs + 2] = rel;
+    rec[4 * rhs + 3] = (double)still;
+  }
+}
+
+// p = z + beta p for active right-hand sides; beta = rz_new/rz_old (standard)
+// or -alpha zq / rz_old (flexible: z^T (r_new - r_old) / rz_old).  rz_new
+// (and zq) come as the nblk partial sums of the preceding dot product; every
+// block finishes them itself, block 0 stores them.
+__global__ void __launch_bounds__(kRedThreads)
+k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ rz_part,
+           const double* __restrict__ zq_part, int nblk, double* __restrict__ rz_new_out,
+           double* __restrict__ zq_out, const double* __restrict__ rz_old,
            const double* __restrict__ alpha, const int* __restrict__ active, int flexible,
            long long n) {
+  __shared__ double sh[kRedThreads];
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
   const long long off = (long long)rhs * n;
-  const double beta = flexible ? (-alpha[rhs] * zq[rhs] / rz_old[rhs]) : (rz_new[rhs] / rz_old[rhs]);
+  const double rz_new = sum_partials(rz_part + rhs * nblk, nblk, sh);
+  double zq = 0.0;
+  if (flexible) {
+    __syncthreads();
+    zq = sum_partials(zq_part + rhs * nblk, nblk, sh);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    rz_new_out[rhs] = rz_new;
+    if (flexible) zq_out[rhs] = zq;
+  }
+  const double beta = flexible ? (-alpha[rhs] * zq / rz_old[rhs]) : (rz_new / rz_old[rhs]);
   const long long stride = (long long)gridDim.x * kRedThreads;
   for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride)
     p[off + i] = z[off + i] + beta * p[off + i];
@@ -163,8 +220,8 @@ hipError_t blas_dot2(const double* a, const double* b, const double* c, const do
   const int g = grid_for(n);
   hipLaunchKernelGGL(k_dot2, dim3(g, nrhs), dim3(kRedThreads), 0, s, a, b, c, d, n, n, n, partial,
                      partial2);
-  hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial, g, out);
-  if (c) hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial2, g, out2);
+  if (out) hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial, g, out);
+  if (c && out2) hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial2, g, out2);
   return hipGetLastError();
 }
 
@@ -189,20 +246,27 @@ hipError_t blas_normalise(double* v, const double* w, const double* nn, long lon
 }
 
 hipError_t blas_update_xr(double* x, double* r, const double* p, const double* q, const double* rz,
-                          const double* pq, const int* active, long long n, int nrhs,
-                          double* alpha, double* partial, double* rr, hipStream_t s) {
+                          const double* pq_part, double* pq, const int* active, long long n,
+                          int nrhs, double* alpha, double* partial, hipStream_t s) {
   const int g = grid_for(n);
-  hipLaunchKernelGGL(k_update_xr, dim3(g, nrhs), dim3(kRedThreads), 0, s, x, r, p, q, rz, pq,
-                     active, n, alpha, partial);
-  hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial, g, rr);
+  hipLaunchKernelGGL(k_update_xr, dim3(g, nrhs), dim3(kRedThreads), 0, s, x, r, p, q, rz, pq_part, g,
+                     pq, active, n, alpha, partial);
   return hipGetLastError();
 }
 
-hipError_t blas_update_p(double* p, const double* z, const double* rz_new, const double* rz_old,
-                         const double* zq, const double* alpha, const int* active, int flexible,
-                         long long n, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_p, dim3(grid_for(n), nrhs), dim3(kRedThreads), 0, s, p, z, rz_new,
-                     rz_old, zq, alpha, active, flexible, n);
+hipError_t blas_cg_check(const double* rr_part, long long n, int nrhs, double* rr, const double* pq,
+                         const double* nb, double rtol, int* active, double* rec, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_check, dim3(nrhs), dim3(kRedThreads), 0, s, rr_part, grid_for(n), rr, pq,
+                     nb, rtol, active, rec);
+  return hipGetLastError();
+}
+
+hipError_t blas_update_p(double* p, const double* z, const double* rz_part, const double* zq_part,
+                         double* rz_new, double* zq, const double* rz_old, const double* alpha,
+                         const int* active, int flexible, long long n, int nrhs, hipStream_t s) {
+  const int g = grid_for(n);
+  hipLaunchKernelGGL(k_update_p, dim3(g, nrhs), dim3(kRedThreads), 0, s, p, z, rz_part, zq_part, g,
+                     rz_new, zq, rz_old, alpha, active, flexible, n);
   return hipGetLastError();
 }
 
