@@ -699,18 +699,22 @@ k_apply(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restri
 }
 
 // ------------------------------------------- apply, face data in registers
-// Where the lines of a patch sit in one wave (3-D Q1 and Q3: TPP = 16 or 64
-// lanes), the face data of the y- and z-neighbours need not pass through LDS.
-// Lane l forms, for its y-line (px, pz) and for the z-face node (px, py) of
-// the same lane number, the couplings alpha, beta of the n face nodes of its
-// x-block from the neighbour's lines along the face normal, and contracts
-// them with the mass row of px in registers; the z-face values are then
-// contracted along y with the lanes of the same px in the y-block (lane
-// offsets E (nu - mu), cross-lane reads).  Every value is the expression of
+// The face data of the y- and z-neighbours need not be gathered per face node
+// into LDS.  Lane l forms, for its y-line (px, pz) and for the z-face node
+// (px, py) of the same lane number, the couplings alpha, beta of the n face
+// nodes of its x-block from the neighbour's lines along the face normal, and
+// contracts them with the mass row of px in registers.  The z-face values are
+// then contracted along y: where the lines of a patch sit in one wave (Q1,
+// Q3: TPP = 16 or 64 lanes) with the lanes of the same px in the y-block
+// (lane offsets E (nu - mu), cross-lane reads), otherwise through a small LDS
+// array of the x-contracted values.  Every value is the expression of
 // gather_ext / ext_mx / extz_mass_x_line / ext_my in the same order, so the
-// result equals k_apply bit for bit; LDS holds only the two tiles (3-D Q3 in
-// FP64: 9 KB per patch instead of 13 KB, 16 patches per CU instead of 12).
-constexpr bool kApplyRF = (D == 3) && (TPP <= 64) && (64 % TPP == 0);
+// result equals k_apply bit for bit.  LDS per patch: the two tiles (Q3 in
+// FP64: 9 KB instead of 13 KB, 16 patches per CU instead of 12), plus
+// 4 E^2 values elsewhere (Q7 in FP64: 78 KB instead of 86 KB, two patches per
+// CU instead of one).
+constexpr bool kApplyRF = (D == 3);
+constexpr bool kZShfl = (TPP <= 64) && (64 % TPP == 0);
 
 // row[nu] = M[mu][nu] for a lane-dependent mu
 template <typename T>
@@ -734,16 +738,22 @@ __device__ __forceinline__ void face_pair(const Tab<K, T>* __restrict__ t, const
                                           int strideN, const T (&row)[n], T& a, T& b) {
   const T half = T(0.5);
   const T sg = t->sigma;
-  T al[n], be[n];
+  // row by row along the normal (n accumulators live, not n^2 values)
+  T g[n], tr[n], al[n], be[n];
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) g[nu] = T(0);
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int nu = 0; nu < n; ++nu) {
+      const T v = c[nu + j * strideN];
+      g[nu] += (SIDE == 0 ? T(kRef.d1[j]) : T(kRef.d0[j])) * v;
+      if (j == (SIDE == 0 ? K : 0)) tr[nu] = v;
+    }
 #pragma unroll
   for (int nu = 0; nu < n; ++nu) {
-    const T* r = c + nu;
-    const T tr = r[(SIDE == 0 ? K : 0) * strideN];
-    T g = T(0);
-#pragma unroll
-    for (int j = 0; j < n; ++j) g += (SIDE == 0 ? T(kRef.d1[j]) : T(kRef.d0[j])) * r[j * strideN];
-    al[nu] = (SIDE == 0) ? (half * g - sg * tr) : (-sg * tr - half * g);
-    be[nu] = (SIDE == 0) ? -half * tr : half * tr;
+    al[nu] = (SIDE == 0) ? (half * g[nu] - sg * tr[nu]) : (-sg * tr[nu] - half * g[nu]);
+    be[nu] = (SIDE == 0) ? -half * tr[nu] : half * tr[nu];
   }
   T sa = T(0), sb = T(0);
 #pragma unroll
@@ -768,8 +778,8 @@ template <typename T, int PPB>
 __global__ void __launch_bounds__(TPP * PPB)
 k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
            T* __restrict__ y, long long ndof) {
-  static_assert(kApplyRF && TPP * PPB <= 64, "one wave per workgroup");
-  constexpr int PP = 2 * TS;
+  static_assert(kApplyRF && (!kZShfl || TPP * PPB <= 64), "cross-lane reads stay in one wave");
+  constexpr int PP = 2 * TS + (kZShfl ? 0 : 4 * NF);
   __shared__ T smem[PPB * PP];
   const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
   const int wl = threadIdx.x & 63;
@@ -805,6 +815,13 @@ k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
       const long long o = (long long)n * (q % n);
       if (!zbl) face_pair<T, 0>(t, xr + cell_index(N, cx, cy, P.lo[2] - 1) * NC + o, n * n, rowx, za0, zb0);
       if (!zbr) face_pair<T, 1>(t, xr + cell_index(N, cx, cy, P.lo[2] + 2) * NC + o, n * n, rowx, za1, zb1);
+    }
+    if constexpr (!kZShfl) {  // x-contracted z-face values for the y-contraction
+      T* wz = B + TS;
+      wz[0 * NF + lane] = za0;
+      wz[1 * NF + lane] = zb0;
+      wz[2 * NF + lane] = za1;
+      wz[3 * NF + lane] = zb1;
     }
     // X0: a = M_x x -> A, b = L_x x -> B
     const int py = lane % E, pz = lane / E;
@@ -843,11 +860,28 @@ k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
   }
   // z-face values contracted along y (all lanes of a patch take part)
   const int muy = q % n;
-  const T zaL = ycontract_lanes<T>(rowy, za0, wl, muy);
-  const T zbL = ycontract_lanes<T>(rowy, zb0, wl, muy);
-  const T zaR = ycontract_lanes<T>(rowy, za1, wl, muy);
-  const T zbR = ycontract_lanes<T>(rowy, zb1, wl, muy);
+  T zaL = T(0), zbL = T(0), zaR = T(0), zbR = T(0);
+  if constexpr (kZShfl) {
+    zaL = ycontract_lanes<T>(rowy, za0, wl, muy);
+    zbL = ycontract_lanes<T>(rowy, zb0, wl, muy);
+    zaR = ycontract_lanes<T>(rowy, za1, wl, muy);
+    zbR = ycontract_lanes<T>(rowy, zb1, wl, muy);
+  }
   __syncthreads();
+  if constexpr (!kZShfl) {
+    if (active) {
+      const T* wz = B + TS;
+      const int f0 = px + E * (q - muy);
+#pragma unroll
+      for (int nu = 0; nu < n; ++nu) zaL += rowy[nu] * wz[0 * NF + f0 + E * nu];
+#pragma unroll
+      for (int nu = 0; nu < n; ++nu) zbL += rowy[nu] * wz[1 * NF + f0 + E * nu];
+#pragma unroll
+      for (int nu = 0; nu < n; ++nu) zaR += rowy[nu] * wz[2 * NF + f0 + E * nu];
+#pragma unroll
+      for (int nu = 0; nu < n; ++nu) zbR += rowy[nu] * wz[3 * NF + f0 + E * nu];
+    }
+  }
   // Z: y = M_z c + L_z d
   if (active) {
     int base, stride;

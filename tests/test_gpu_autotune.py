@@ -120,11 +120,13 @@ def test_two_wave_shapes_are_bitwise_one_wave(tmp_path, dim, k, L, variant, prec
         assert torch.equal(outs[one][1], outs[two][1])
 
 
-@pytest.mark.parametrize("dim,k,L", [(3, 1, 3), (3, 3, 2), (3, 3, 1), (3, 2, 2)])
+@pytest.mark.parametrize("dim,k,L", [(3, 1, 3), (3, 3, 2), (3, 3, 1), (3, 2, 2), (3, 4, 1), (3, 5, 1),
+                                     (3, 6, 1), (3, 7, 1), (2, 3, 3)])
 def test_register_face_apply_is_bitwise_lds_apply(tmp_path, dim, k, L):
-    """Apply shape 2 (neighbour face data contracted in registers and across
-    lanes instead of through LDS; 3-D Q1 and Q3) evaluates every output with
-    the operations of shape 0: equal bit for bit, on every right-hand side."""
+    """Apply shape 2 (neighbour face data contracted in registers, then across
+    lanes (3-D Q1, Q3) or through a small LDS array (other degrees); in 2-D
+    the same as shape 0) evaluates every output with the operations of shape
+    0: equal bit for bit, on every right-hand side."""
     note(f"register-face apply bitwise d={dim} k={k} L={L}")
     nrhs = 3
     X = inputs.uniform(71, (nrhs, 2 ** ((L + 1) * dim) * (k + 1) ** dim))
