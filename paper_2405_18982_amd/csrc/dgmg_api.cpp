@@ -160,6 +160,9 @@ struct dgmg_ctx {
   Tuning tune_smooth[2][21];  // per precision and level
   hipStream_t cap_stream = nullptr;
   std::vector<hipGraphExec_t> vc_graph;  // index nrhs - 1
+  // the FP32 V-cycle alone (finest-level b32 -> x32), for the CG with an
+  // FP32 V-cycle, whose vector kernels convert on the fly
+  std::vector<hipGraphExec_t> vc_graph32;
   // GMRES workspace (finest level, one right-hand side): Krylov basis V
   // (gm_cap + 1 vectors), preconditioned directions Z (gm_cap vectors),
   // device scalars and their pinned host mirror, partial sums
@@ -456,11 +459,12 @@ dgmg_status precondition(dgmg_ctx* c, const double* r, double* z, int nrhs) {
 }
 
 void drop_graphs(dgmg_ctx* c) {
-  for (hipGraphExec_t& g : c->vc_graph)
-    if (g) {
-      hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  for (auto* v : {&c->vc_graph, &c->vc_graph32})
+    for (hipGraphExec_t& g : *v)
+      if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
+      }
 }
 
 // Wait for an event by polling it (no sleep on the stream: the host sees the
@@ -476,11 +480,19 @@ dgmg_status poll_event(dgmg_ctx* c, hipEvent_t ev) {
 }
 
 // z = V(r) for the CG: replay (capturing on first use) the graph of the
-// V-cycle on the CG workspace for this nrhs.
-dgmg_status precondition_cg(dgmg_ctx* c, int nrhs) {
-  if (!c->use_graph) return precondition(c, c->r, c->z, nrhs);
-  if ((int)c->vc_graph.size() < c->nrhs_max) c->vc_graph.resize(c->nrhs_max, nullptr);
-  hipGraphExec_t& ex = c->vc_graph[nrhs - 1];
+// V-cycle on the CG workspace for this nrhs.  raw32 (FP32 V-cycle only): the
+// V-cycle alone from the finest level's b32 to its x32, the conversions left
+// to the CG's vector kernels.
+dgmg_status precondition_cg(dgmg_ctx* c, int nrhs, bool raw32 = false) {
+  auto body = [&]() -> dgmg_status {
+    if (!raw32) return precondition(c, c->r, c->z, nrhs);
+    Level& T = c->lv[c->L];
+    return vcycle_T<float>(c, T.b32, T.x32, nrhs);
+  };
+  if (!c->use_graph) return body();
+  auto& cache = raw32 ? c->vc_graph32 : c->vc_graph;
+  if ((int)cache.size() < c->nrhs_max) cache.resize(c->nrhs_max, nullptr);
+  hipGraphExec_t& ex = cache[nrhs - 1];
   if (!ex) {
     if (!c->cap_stream) HIPCHK(c, hipStreamCreate(&c->cap_stream));
     // level buffers must exist before capture (allocation is not capturable)
@@ -492,7 +504,7 @@ dgmg_status precondition_cg(dgmg_ctx* c, int nrhs) {
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
     dgmg_status st = DGMG_OK;
-    if (e == hipSuccess) st = precondition(c, c->r, c->z, nrhs);
+    if (e == hipSuccess) st = body();
     hipError_t e2 = (e == hipSuccess) ? hipStreamEndCapture(c->cap_stream, &graph) : e;
     c->stream = user;
     if (st != DGMG_OK) {
@@ -784,10 +796,27 @@ DGMG_API dgmg_status dgmg_pcg_solve(dgmg_ctx* c, const double* b, double* x, int
   for (int j = 0; j < nrhs; ++j) c->hnb[j] = nb[j];
   HIPCHK(c, hipMemcpyAsync(c->nb, c->hnb, sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->active, c->hact, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-  RET(precondition_cg(c, nrhs));
-  HIPCHK(c, dgmg::blas_dot2(c->r, c->z, nullptr, nullptr, n, nrhs, c->partial, nullptr, rzb[0],
-                            nullptr, s));
-  HIPCHK(c, hipMemcpyAsync(c->p, c->z, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, s));
+  // FP32 V-cycle: it runs from the finest level's b32 to its x32 and the
+  // vector kernels convert on the way (the update of x and r writes
+  // b32 = (float) r, the dot products and the update of p read z = x32 in
+  // FP64), the same values as converting whole vectors around the V-cycle
+  float* b32 = nullptr;
+  const float* z32 = nullptr;
+  if (flexible) {
+    RET(ensure_levels<float>(c, c->L));
+    b32 = c->lv[c->L].b32;
+    z32 = c->lv[c->L].x32;
+    HIPCHK(c, dgmg::blas_f64_to_f32(c->r, b32, n * nrhs, s));
+    RET(precondition_cg(c, nrhs, true));
+    HIPCHK(c, dgmg::blas_dot2_z32(c->r, z32, nullptr, nullptr, n, nrhs, c->partial, nullptr, s));
+    HIPCHK(c, dgmg::blas_finalize(c->partial, n, nrhs, rzb[0], s));
+    HIPCHK(c, dgmg::blas_f32_to_f64(z32, c->p, n * nrhs, s));
+  } else {
+    RET(precondition_cg(c, nrhs));
+    HIPCHK(c, dgmg::blas_dot2(c->r, c->z, nullptr, nullptr, n, nrhs, c->partial, nullptr, rzb[0],
+                              nullptr, s));
+    HIPCHK(c, hipMemcpyAsync(c->p, c->z, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, s));
+  }
   dgmg_status status = DGMG_ERR_NOT_CONVERGED;
   for (int it = 1; it <= maxit; ++it) {
     double* rz_old = rzb[(it - 1) & 1];
@@ -800,7 +829,7 @@ DGMG_API dgmg_status dgmg_pcg_solve(dgmg_ctx* c, const double* b, double* x, int
     // next iteration) and records (|r|^2, p^T q, relres, active) in pinned
     // host memory; the host polls the event instead of sleeping on the stream
     HIPCHK(c, dgmg::blas_update_xr(x, c->r, c->p, c->q, rz_old, c->partial, pq, c->active, n, nrhs,
-                                   alpha, c->partial2, s));
+                                   alpha, c->partial2, b32, s));
     HIPCHK(c, dgmg::blas_cg_check(c->partial2, n, nrhs, rr, pq, c->nb, rtol, c->active, c->rec_dev, s));
     HIPCHK(c, hipEventRecord(c->ev_check, s));
     RET(poll_event(c, c->ev_check));
@@ -816,12 +845,18 @@ DGMG_API dgmg_status dgmg_pcg_solve(dgmg_ctx* c, const double* b, double* x, int
       any = any || c->hact[j];
     }
     if (!any) { status = DGMG_OK; break; }
-    RET(precondition_cg(c, nrhs));
+    RET(precondition_cg(c, nrhs, flexible));
     // r^T z (and z^T q) stay as partial sums; the update of p finishes them
-    HIPCHK(c, dgmg::blas_dot2(c->r, c->z, flexible ? c->z : nullptr, flexible ? c->q : nullptr, n,
-                              nrhs, c->partial, c->partial2, nullptr, nullptr, s));
-    HIPCHK(c, dgmg::blas_update_p(c->p, c->z, c->partial, c->partial2, rz_new, zq, rz_old, alpha,
-                                  c->active, flexible, n, nrhs, s));
+    if (flexible) {
+      HIPCHK(c, dgmg::blas_dot2_z32(c->r, z32, z32, c->q, n, nrhs, c->partial, c->partial2, s));
+      HIPCHK(c, dgmg::blas_update_p_z32(c->p, z32, c->partial, c->partial2, rz_new, zq, rz_old, alpha,
+                                        c->active, 1, n, nrhs, s));
+    } else {
+      HIPCHK(c, dgmg::blas_dot2(c->r, c->z, nullptr, nullptr, n, nrhs, c->partial, c->partial2,
+                                nullptr, nullptr, s));
+      HIPCHK(c, dgmg::blas_update_p(c->p, c->z, c->partial, c->partial2, rz_new, zq, rz_old, alpha,
+                                    c->active, 0, n, nrhs, s));
+    }
   }
   HIPCHK(c, hipStreamSynchronize(s));
   if (status != DGMG_OK) c->err = "maximum number of iterations reached";

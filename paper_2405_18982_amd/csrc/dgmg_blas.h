@@ -18,9 +18,10 @@ hipError_t blas_dot2(const double* a, const double* b, const double* c, const do
 // CG update x += alpha p, r -= alpha q, alpha = rz / pq per active right-hand
 // side, with p^T q finished from the partial sums pq_part of blas_dot2 (and
 // stored to pq); partial: first-stage sums of |r|^2 (must not alias pq_part).
+// r32 != nullptr: also r32 = (float) r for the active right-hand sides.
 hipError_t blas_update_xr(double* x, double* r, const double* p, const double* q, const double* rz,
                           const double* pq_part, double* pq, const int* active, long long n,
-                          int nrhs, double* alpha, double* partial, hipStream_t s);
+                          int nrhs, double* alpha, double* partial, float* r32, hipStream_t s);
 // rr = |r|^2 from rr_part; active &&= sqrt(rr) / nb > rtol; rec (device
 // address of host-visible memory, 4 doubles per right-hand side) =
 // (rr, pq, sqrt(rr) / nb, active).
@@ -31,6 +32,16 @@ hipError_t blas_cg_check(const double* rr_part, long long n, int nrhs, double* r
 hipError_t blas_update_p(double* p, const double* z, const double* rz_part, const double* zq_part,
                          double* rz_new, double* zq, const double* rz_old, const double* alpha,
                          const int* active, int flexible, long long n, int nrhs, hipStream_t s);
+// out[r] = sum of the first-stage partial sums that blas_dot2 left for
+// vectors of length n (the second stage it skips when out == nullptr).
+hipError_t blas_finalize(const double* partial, long long n, int nrhs, double* out, hipStream_t s);
+// The same two steps with z the FP32 output of the V-cycle (its values taken
+// exactly in FP64): partial sums of r^T z (and, zc = z, z^T q), and p update.
+hipError_t blas_dot2_z32(const double* r, const float* z, const float* zc, const double* q,
+                         long long n, int nrhs, double* partial, double* partial2, hipStream_t s);
+hipError_t blas_update_p_z32(double* p, const float* z, const double* rz_part, const double* zq_part,
+                             double* rz_new, double* zq, const double* rz_old, const double* alpha,
+                             const int* active, int flexible, long long n, int nrhs, hipStream_t s);
 // out[i] = V_i . w for the m vectors V_i = V + i n (partial: m * kRedBlocks).
 hipError_t blas_multi_dot(const double* V, const double* w, long long n, int m, double* partial,
                           double* out, hipStream_t s);

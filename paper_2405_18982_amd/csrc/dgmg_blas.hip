@@ -25,9 +25,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // partial[r][blk] = sum over the block's grid-stride share of a_r . b_r
 // (and, if c != nullptr, partial2 = c_r . d_r); vector r of a starts at
-// r * sa, of b at r * sb (sb = 0: one b against every a_r)
+// r * sa, of b at r * sb (sb = 0: one b against every a_r).  b and c may be
+// FP32 vectors, read as the FP64 values they hold exactly.
+template <typename TB>
 __global__ void __launch_bounds__(kRedThreads)
-k_dot2(const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ c,
+k_dot2(const double* __restrict__ a, const TB* __restrict__ b, const TB* __restrict__ c,
        const double* __restrict__ d, long long n, long long sa, long long sb,
        double* __restrict__ partial, double* __restrict__ partial2) {
   __shared__ double sh[kRedThreads];
@@ -36,8 +38,8 @@ k_dot2(const double* __restrict__ a, const double* __restrict__ b, const double*
   double s1 = 0.0, s2 = 0.0;
   const long long stride = (long long)gridDim.x * kRedThreads;
   for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
-    s1 += a[off + i] * b[offb + i];
-    if (c) s2 += c[off + i] * d[off + i];
+    s1 += a[off + i] * (double)b[offb + i];
+    if (c) s2 += (double)c[off + i] * d[off + i];
   }
   const double r1 = block_sum(s1, sh);
   if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r1;
@@ -77,7 +79,7 @@ k_update_xr(double* __restrict__ x, double* __restrict__ r, const double* __rest
             const double* __restrict__ q, const double* __restrict__ rz,
             const double* __restrict__ pq_part, int nblk, double* __restrict__ pq_out,
             const int* __restrict__ active, long long n, double* __restrict__ alpha_out,
-            double* __restrict__ partial) {
+            double* __restrict__ partial, float* __restrict__ r32) {
   __shared__ double sh[kRedThreads];
   const int rhs = blockIdx.y;
   const long long off = (long long)rhs * n;
@@ -97,6 +99,7 @@ k_update_xr(double* __restrict__ x, double* __restrict__ r, const double* __rest
       x[off + i] += alpha * p[off + i];
       ri -= alpha * q[off + i];
       r[off + i] = ri;
+      if (r32) r32[off + i] = (float)ri;  // right-hand side of an FP32 V-cycle
     }
     s += ri * ri;
   }
@@ -132,9 +135,11 @@ k_cg_check(const double* __restrict__ rr_part, int nblk, double* __restrict__ rr
 // p = z + beta p for active right-hand sides; beta = rz_new/rz_old (standard)
 // or -alpha zq / rz_old (flexible: z^T (r_new - r_old) / rz_old).  rz_new
 // (and zq) come as the nblk partial sums of the preceding dot product; every
-// block finishes them itself, block 0 stores them.
+// block finishes them itself, block 0 stores them.  z may be the FP32 output
+// of the V-cycle, read as the FP64 values it holds exactly.
+template <typename TZ>
 __global__ void __launch_bounds__(kRedThreads)
-k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ rz_part,
+k_update_p(double* __restrict__ p, const TZ* __restrict__ z, const double* __restrict__ rz_part,
            const double* __restrict__ zq_part, int nblk, double* __restrict__ rz_new_out,
            double* __restrict__ zq_out, const double* __restrict__ rz_old,
            const double* __restrict__ alpha, const int* __restrict__ active, int flexible,
@@ -156,7 +161,7 @@ k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* _
   const double beta = flexible ? (-alpha[rhs] * zq / rz_old[rhs]) : (rz_new / rz_old[rhs]);
   const long long stride = (long long)gridDim.x * kRedThreads;
   for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride)
-    p[off + i] = z[off + i] + beta * p[off + i];
+    p[off + i] = (double)z[off + i] + beta * p[off + i];
 }
 
 template <typename S, typename T>
@@ -218,7 +223,7 @@ hipError_t blas_dot2(const double* a, const double* b, const double* c, const do
                      long long n, int nrhs, double* partial, double* partial2, double* out,
                      double* out2, hipStream_t s) {
   const int g = grid_for(n);
-  hipLaunchKernelGGL(k_dot2, dim3(g, nrhs), dim3(kRedThreads), 0, s, a, b, c, d, n, n, n, partial,
+  hipLaunchKernelGGL(k_dot2<double>, dim3(g, nrhs), dim3(kRedThreads), 0, s, a, b, c, d, n, n, n, partial,
                      partial2);
   if (out) hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial, g, out);
   if (c && out2) hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial2, g, out2);
@@ -228,7 +233,7 @@ hipError_t blas_dot2(const double* a, const double* b, const double* c, const do
 hipError_t blas_multi_dot(const double* V, const double* w, long long n, int m, double* partial,
                           double* out, hipStream_t s) {
   const int g = grid_for(n);
-  hipLaunchKernelGGL(k_dot2, dim3(g, m), dim3(kRedThreads), 0, s, V, w, nullptr, nullptr, n, n, 0LL,
+  hipLaunchKernelGGL(k_dot2<double>, dim3(g, m), dim3(kRedThreads), 0, s, V, w, nullptr, nullptr, n, n, 0LL,
                      partial, nullptr);
   hipLaunchKernelGGL(k_finalize, dim3(m), dim3(kRedThreads), 0, s, partial, g, out);
   return hipGetLastError();
@@ -247,10 +252,10 @@ hipError_t blas_normalise(double* v, const double* w, const double* nn, long lon
 
 hipError_t blas_update_xr(double* x, double* r, const double* p, const double* q, const double* rz,
                           const double* pq_part, double* pq, const int* active, long long n,
-                          int nrhs, double* alpha, double* partial, hipStream_t s) {
+                          int nrhs, double* alpha, double* partial, float* r32, hipStream_t s) {
   const int g = grid_for(n);
   hipLaunchKernelGGL(k_update_xr, dim3(g, nrhs), dim3(kRedThreads), 0, s, x, r, p, q, rz, pq_part, g,
-                     pq, active, n, alpha, partial);
+                     pq, active, n, alpha, partial, r32);
   return hipGetLastError();
 }
 
@@ -265,8 +270,29 @@ hipError_t blas_update_p(double* p, const double* z, const double* rz_part, cons
                          double* rz_new, double* zq, const double* rz_old, const double* alpha,
                          const int* active, int flexible, long long n, int nrhs, hipStream_t s) {
   const int g = grid_for(n);
-  hipLaunchKernelGGL(k_update_p, dim3(g, nrhs), dim3(kRedThreads), 0, s, p, z, rz_part, zq_part, g,
-                     rz_new, zq, rz_old, alpha, active, flexible, n);
+  hipLaunchKernelGGL(k_update_p<double>, dim3(g, nrhs), dim3(kRedThreads), 0, s, p, z, rz_part, zq_part,
+                     g, rz_new, zq, rz_old, alpha, active, flexible, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_finalize(const double* partial, long long n, int nrhs, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial, grid_for(n), out);
+  return hipGetLastError();
+}
+
+hipError_t blas_dot2_z32(const double* r, const float* z, const float* zc, const double* q,
+                         long long n, int nrhs, double* partial, double* partial2, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot2<float>, dim3(grid_for(n), nrhs), dim3(kRedThreads), 0, s, r, z, zc, q, n,
+                     n, n, partial, partial2);
+  return hipGetLastError();
+}
+
+hipError_t blas_update_p_z32(double* p, const float* z, const double* rz_part, const double* zq_part,
+                             double* rz_new, double* zq, const double* rz_old, const double* alpha,
+                             const int* active, int flexible, long long n, int nrhs, hipStream_t s) {
+  const int g = grid_for(n);
+  hipLaunchKernelGGL(k_update_p<float>, dim3(g, nrhs), dim3(kRedThreads), 0, s, p, z, rz_part, zq_part,
+                     g, rz_new, zq, rz_old, alpha, active, flexible, n);
   return hipGetLastError();
 }
 
