@@ -229,11 +229,57 @@ __device__ __forceinline__ const T* fd_lam(const Tab<K, T>* __restrict__ t, int 
   return SP == SP_FULL ? t->lamf[ty] : SP == SP_CLAMPED ? t->lamc[ty] : t->lam[ty];
 }
 
+// Interior patches (type 0) on the Dirichlet space: the 1-D problem is
+// symmetric under the reflection p -> E-1-p, and the host computes its
+// eigenvectors on the even and the odd subspace (columns q < h even,
+// h <= q < 2h odd, h = n - 1).  S^T then contracts sums v+ and differences v-
+// of mirrored nodes with half columns, and S forms the even part e and odd
+// part d of each mirrored pair: 2 h^2 multiply-adds instead of 4 h^2.  Used
+// from Q4 on: measured on a smoothing step, 4-12% faster for Q4..Q7, 4-5%
+// slower for Q3 (h = 3), where the dense contraction stays.
+constexpr int kEOH = n - 1;
+constexpr bool kEO = (K >= 4);
+
+template <typename T>
+__device__ __forceinline__ void eo_split(const Line<T>& v, T (&vp)[kEOH], T (&vm)[kEOH]) {
+#pragma unroll
+  for (int k = 0; k < kEOH; ++k) {
+    vp[k] = v.v[1 + k] + v.v[E - 2 - k];
+    vm[k] = v.v[1 + k] - v.v[E - 2 - k];
+  }
+}
+// coefficient q < 2h of S^T v
+template <typename T>
+__device__ __forceinline__ T eo_coef(const T* S, const T (&vp)[kEOH], const T (&vm)[kEOH], int q) {
+  T s = T(0);
+#pragma unroll
+  for (int k = 0; k < kEOH; ++k) s += S[(1 + k) * E + q] * (q < kEOH ? vp[k] : vm[k]);
+  return s;
+}
+// even and odd parts of the outputs at nodes 1 + k and E - 2 - k of S v
+template <typename T>
+__device__ __forceinline__ void eo_pair(const T* S, const Line<T>& v, int k, T& e, T& d) {
+  T se = T(0), sd = T(0);
+#pragma unroll
+  for (int q = 0; q < kEOH; ++q) se += S[(1 + k) * E + q] * v.v[q];
+#pragma unroll
+  for (int q = 0; q < kEOH; ++q) sd += S[(1 + k) * E + kEOH + q] * v.v[kEOH + q];
+  e = se;
+  d = sd;
+}
+
 // o[q] = sum_p S[p][q] v[p]
 template <typename T, int TY, int SP>
 __device__ __forceinline__ void line_St_t(const Tab<K, T>* __restrict__ t, const Line<T>& v, Line<T>& o) {
   using B = FDB<SP, TY>;
   const T* S = fd_S<T, SP>(t, TY);
+  if constexpr (kEO && SP == SP_DIR && TY == 0) {
+    T vp[kEOH], vm[kEOH];
+    eo_split<T>(v, vp, vm);
+#pragma unroll
+    for (int q = 0; q < E; ++q) o.v[q] = (q < 2 * kEOH) ? eo_coef<T>(S, vp, vm, q) : T(0);
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     T s = T(0);
@@ -249,6 +295,18 @@ template <typename T, int TY, int SP>
 __device__ __forceinline__ void line_S_t(const Tab<K, T>* __restrict__ t, const Line<T>& v, Line<T>& o) {
   using B = FDB<SP, TY>;
   const T* S = fd_S<T, SP>(t, TY);
+  if constexpr (kEO && SP == SP_DIR && TY == 0) {
+    o.v[0] = T(0);
+    o.v[E - 1] = T(0);
+#pragma unroll
+    for (int k = 0; k < kEOH; ++k) {
+      T e, d;
+      eo_pair<T>(S, v, k, e, d);
+      o.v[1 + k] = e + d;
+      o.v[E - 2 - k] = e - d;
+    }
+    return;
+  }
 #pragma unroll
   for (int p = 0; p < E; ++p) {
     T s = T(0);
@@ -1296,6 +1354,16 @@ template <typename T, int TY, int SP, int H>
 __device__ __forceinline__ void half_St_t(const Tab<K, T>* __restrict__ t, const Line<T>& v, Half<T>& o) {
   using B = FDB<SP, TY>;
   const T* S = fd_S<T, SP>(t, TY);
+  if constexpr (kEO && SP == SP_DIR && TY == 0) {
+    T vp[kEOH], vm[kEOH];
+    eo_split<T>(v, vp, vm);
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      const int q = H * n + j;
+      o.v[j] = (q < 2 * kEOH) ? eo_coef<T>(S, vp, vm, q) : T(0);
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < n; ++j) {
     const int q = H * n + j;
@@ -1312,6 +1380,21 @@ template <typename T, int TY, int SP, int H>
 __device__ __forceinline__ void half_S_t(const Tab<K, T>* __restrict__ t, const Line<T>& v, Half<T>& o) {
   using B = FDB<SP, TY>;
   const T* S = fd_S<T, SP>(t, TY);
+  if constexpr (kEO && SP == SP_DIR && TY == 0) {
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      const int p = H * n + j;
+      if (p == 0 || p == E - 1) {
+        o.v[j] = T(0);
+      } else {
+        const int k = (p <= kEOH) ? p - 1 : E - 2 - p;
+        T e, d;
+        eo_pair<T>(S, v, k, e, d);
+        o.v[j] = (p <= kEOH) ? e + d : e - d;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < n; ++j) {
     const int p = H * n + j;

@@ -262,12 +262,41 @@ bool build_host_tables(int k, double sigma, HostTables& T, const char** err) {
         L[(E - 1) * E + n + j] -= 0.5 * T.d1[j];
         L[(n + j) * E + E - 1] -= 0.5 * T.d1[j];
       }
-    std::vector<int> keep;
-    for (int p = 0; p < E; ++p) {
-      const bool drop = (p == 0 && !(t & 1)) || (p == E - 1 && !(t & 2));
-      if (!drop) keep.push_back(p);
+    if (t == 0) {
+      // interior patch: the Dirichlet space (nodes 1 .. E-2) and both 1-D
+      // matrices are symmetric under the reflection p -> E-1-p, so the
+      // eigenvectors split into even and odd ones.  They are computed on the
+      // even and the odd subspace separately, which makes the symmetry exact:
+      // columns q < h even, h <= q < 2h odd (h = n - 1), as the kernels'
+      // even-odd contractions assume.
+      const int h = n - 1;
+      std::vector<double> Cp(E * h, 0.0), Cm(E * h, 0.0), Sp, lp, Sm, lm;
+      for (int j = 0; j < h; ++j) {
+        Cp[(1 + j) * h + j] = 1.0;
+        Cp[(E - 2 - j) * h + j] = 1.0;
+        Cm[(1 + j) * h + j] = 1.0;
+        Cm[(E - 2 - j) * h + j] = -1.0;
+      }
+      if (!basis_eigenpairs(L, Mp, E, Cp, h, Sp, lp, err)) return false;
+      if (!basis_eigenpairs(L, Mp, E, Cm, h, Sm, lm, err)) return false;
+      T.S[t].assign(E * E, 0.0);
+      T.lam[t].assign(E, std::numeric_limits<double>::infinity());
+      for (int q = 0; q < h; ++q) {
+        T.lam[t][q] = lp[q];
+        T.lam[t][h + q] = lm[q];
+        for (int p = 0; p < E; ++p) {
+          T.S[t][p * E + q] = Sp[p * E + q];
+          T.S[t][p * E + h + q] = Sm[p * E + q];
+        }
+      }
+    } else {
+      std::vector<int> keep;
+      for (int p = 0; p < E; ++p) {
+        const bool drop = (p == 0 && !(t & 1)) || (p == E - 1 && !(t & 2));
+        if (!drop) keep.push_back(p);
+      }
+      if (!patch_eigenpairs(L, Mp, E, keep, T.S[t], T.lam[t], err)) return false;
     }
-    if (!patch_eigenpairs(L, Mp, E, keep, T.S[t], T.lam[t], err)) return false;
     // Full kernel: every node of the two cells
     std::vector<int> all(E);
     for (int p = 0; p < E; ++p) all[p] = p;

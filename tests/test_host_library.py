@@ -101,6 +101,14 @@ def test_patch_eigenpairs_match_oracle(k, sigma_rule):
             assert np.allclose(Sk.T @ Mt @ Sk, np.eye(m), atol=1e-11)
             Linv = Sk @ np.diag(1.0 / lam[:m]) @ Sk.T
             assert np.abs(Linv @ Lt - np.eye(m)).max() < 1e-10
+            if t == 0:
+                # interior patch: columns q < k even, k <= q < 2k odd under
+                # the reflection of the patch, exactly (the kernels contract
+                # half lines on that structure)
+                E = 2 * (k + 1)
+                R = S[::-1, :]
+                assert np.array_equal(R[:, :k], S[:, :k])
+                assert np.array_equal(R[:, k:2 * k], -S[:, k:2 * k])
             # Full kernel: the whole patch, every slot used
             Sf, lamf = dgmg.patch_eigen(k, sigma, t, dgmg.SMOOTH_FULL)
             E = 2 * (k + 1)
