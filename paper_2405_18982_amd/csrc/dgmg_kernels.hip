@@ -95,11 +95,89 @@ __device__ __forceinline__ void store_line(T* s, int base, int stride, const Lin
   for (int p = 0; p < E; ++p) s[base + p * stride] = L.v[p];
 }
 
+// Even-odd form of the cell blocks (from Q4 on).  M and the consistency
+// block Lcons are symmetric under the reflection of a cell (mu -> n-1-mu,
+// nu -> n-1-nu), so B w for a cell line w is formed from sums ve and
+// differences vo of mirrored values: the even part e = A ve (+ the middle
+// column times the middle value for odd n), the odd part d = Bo vo, outputs
+// e + d and e - d at mirrored rows (and the middle row from ve for odd n),
+// with A, Bo the half-sums and half-differences of mirrored columns.  Fewer
+// multiply-adds: 48 instead of 64 for n = 8.
+constexpr bool kEOC = (K >= 4);
+constexpr int kHN = n / 2;
+constexpr bool kOddN = (n % 2) == 1;
+struct EOCell {
+  double A[kHN * kHN];
+  double Bo[kHN * kHN];
+  double colm[kHN + 1];  // middle column (rows < kHN), odd n
+  double rowm[kHN + 1];  // middle row (columns < kHN, then the diagonal), odd n
+};
+constexpr EOCell make_eo_cell(const double (&B)[n * n]) {
+  EOCell r{};
+  for (int mu = 0; mu < kHN; ++mu)
+    for (int j = 0; j < kHN; ++j) {
+      r.A[mu * kHN + j] = 0.5 * (B[mu * n + j] + B[mu * n + n - 1 - j]);
+      r.Bo[mu * kHN + j] = 0.5 * (B[mu * n + j] - B[mu * n + n - 1 - j]);
+    }
+  if (kOddN) {
+    for (int mu = 0; mu < kHN; ++mu) r.colm[mu] = B[mu * n + kHN];
+    for (int j = 0; j < kHN; ++j) r.rowm[j] = B[kHN * n + j];
+    r.rowm[kHN] = B[kHN * n + kHN];
+  }
+  return r;
+}
+static constexpr EOCell kEOM = make_eo_cell(kRef.M);
+static constexpr EOCell kEOL = make_eo_cell(kRef.Lcons);
+
+// bl = B w for the cell c of patch line v (MASS: B = M, else Lcons)
+template <typename T, bool MASS>
+__device__ __forceinline__ void cell_eo(const Line<T>& v, int c, T (&bl)[n]) {
+  constexpr const EOCell& C = MASS ? kEOM : kEOL;
+  T ve[kHN], vo[kHN];
+#pragma unroll
+  for (int j = 0; j < kHN; ++j) {
+    ve[j] = v.v[c * n + j] + v.v[c * n + n - 1 - j];
+    vo[j] = v.v[c * n + j] - v.v[c * n + n - 1 - j];
+  }
+#pragma unroll
+  for (int mu = 0; mu < kHN; ++mu) {
+    T se = T(0), so = T(0);
+#pragma unroll
+    for (int j = 0; j < kHN; ++j) se += T(C.A[mu * kHN + j]) * ve[j];
+    if constexpr (kOddN) se += T(C.colm[mu]) * v.v[c * n + kHN];
+#pragma unroll
+    for (int j = 0; j < kHN; ++j) so += T(C.Bo[mu * kHN + j]) * vo[j];
+    bl[mu] = se + so;
+    bl[n - 1 - mu] = se - so;
+  }
+  if constexpr (kOddN) {
+    T sm = T(0);
+#pragma unroll
+    for (int j = 0; j < kHN; ++j) sm += T(C.rowm[j]) * ve[j];
+    sm += T(C.rowm[kHN]) * v.v[c * n + kHN];
+    bl[kHN] = sm;
+  }
+}
+
 // o = blockdiag(M, M) v; the end outputs o[0] and o[E-1] only when need0 /
 // needE (wave-uniform): smoothers drop them on interior patch faces
 template <typename T>
 __device__ __forceinline__ void line_mass(const Tab<K, T>* __restrict__ t, const Line<T>& v, Line<T>& o,
                                           bool need0 = true, bool needE = true) {
+  if constexpr (kEOC) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      T bl[n];
+      cell_eo<T, true>(v, c, bl);
+#pragma unroll
+      for (int mu = 0; mu < n; ++mu) {
+        const int p = c * n + mu;
+        if ((p == 0 && !need0) || (p == E - 1 && !needE)) continue;
+        o.v[p] = bl[mu];
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -145,18 +223,25 @@ __device__ __forceinline__ void line_sipg(const Tab<K, T>* __restrict__ t, const
   const T sg = t->sigma;
   const T half = T(0.5);
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+  for (int c = 0; c < 2; ++c) {
+    T bl[n];
+    if constexpr (kEOC) cell_eo<T, false>(v, c, bl);
 #pragma unroll
     for (int mu = 0; mu < n; ++mu) {
       const int p = c * n + mu;
       if ((p == 0 && !need0) || (p == E - 1 && !needE)) continue;
       T s = ACC ? o.v[p] : T(0);
+      if constexpr (kEOC) {
+        s += bl[mu];
+      } else {
 #pragma unroll
-      for (int nu = 0; nu < n; ++nu) s += T(kRef.Lcons[mu * n + nu]) * v.v[c * n + nu];
+        for (int nu = 0; nu < n; ++nu) s += T(kRef.Lcons[mu * n + nu]) * v.v[c * n + nu];
+      }
       if (mu == 0) s += sg * v.v[c * n];          // penalty part of the cell block
       if (mu == n - 1) s += sg * v.v[c * n + n - 1];
       o.v[p] = s;
     }
+  }
   // face between the two patch cells
   const T tR = v.v[n];      // trace of the right cell at its x=0 side
   const T tL = v.v[n - 1];  // trace of the left cell at its x=1 side
@@ -565,12 +650,19 @@ __device__ __forceinline__ void extz_mass_x_line(const Tab<K, T>* __restrict__ t
   const int py = j % E;
   const int arr = j / E;  // (side * NCOMP + comp)
   T* a = ext + extz_base<NCOMP>() + arr * NF + py * E;
-  Line<T> v, o;
+  T v[E];
 #pragma unroll
-  for (int p = 0; p < E; ++p) v.v[p] = a[p];
-  line_mass<T>(t, v, o);
+  for (int p = 0; p < E; ++p) v[p] = a[p];
+  // dense mass rows (face data, contracted the same way wherever it is used)
 #pragma unroll
-  for (int p = 0; p < E; ++p) a[p] = o.v[p];
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int mu = 0; mu < n; ++mu) {
+      T s = T(0);
+#pragma unroll
+      for (int nu = 0; nu < n; ++nu) s += T(kRef.M[mu * n + nu]) * v[c * n + nu];
+      a[c * n + mu] = s;
+    }
 }
 template <typename T, int NCOMP>
 __device__ __forceinline__ Sides<T> zline_sides(const Tab<K, T>* __restrict__ t, const T* ext,
@@ -1275,6 +1367,16 @@ __device__ __forceinline__ constexpr bool half_end(int mu) { return H == 0 ? mu 
 // o = (blockdiag(M, M) v) on cell H; the patch-end output only if needEnd
 template <typename T, int H>
 __device__ __forceinline__ void half_mass(const Line<T>& v, Half<T>& o, bool needEnd) {
+  if constexpr (kEOC) {
+    T bl[n];
+    cell_eo<T, true>(v, H, bl);
+#pragma unroll
+    for (int mu = 0; mu < n; ++mu) {
+      if (half_end<H>(mu) && !needEnd) continue;
+      o.v[mu] = bl[mu];
+    }
+    return;
+  }
 #pragma unroll
   for (int mu = 0; mu < n; ++mu) {
     if (half_end<H>(mu) && !needEnd) continue;
@@ -1292,12 +1394,18 @@ __device__ __forceinline__ void half_sipg(const Tab<K, T>* __restrict__ t, const
                                           const Sides<T>& sd, Half<T>& o, bool needEnd) {
   const T sg = t->sigma;
   const T half = T(0.5);
+  T bl[n];
+  if constexpr (kEOC) cell_eo<T, false>(v, H, bl);
 #pragma unroll
   for (int mu = 0; mu < n; ++mu) {
     if (half_end<H>(mu) && !needEnd) continue;
     T s = ACC ? o.v[mu] : T(0);
+    if constexpr (kEOC) {
+      s += bl[mu];
+    } else {
 #pragma unroll
-    for (int nu = 0; nu < n; ++nu) s += T(kRef.Lcons[mu * n + nu]) * v.v[H * n + nu];
+      for (int nu = 0; nu < n; ++nu) s += T(kRef.Lcons[mu * n + nu]) * v.v[H * n + nu];
+    }
     if (mu == 0) s += sg * v.v[H * n];
     if (mu == n - 1) s += sg * v.v[H * n + n - 1];
     o.v[mu] = s;
