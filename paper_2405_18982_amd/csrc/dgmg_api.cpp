@@ -583,6 +583,10 @@ DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int sm
   }
   c->nrhs_max = nrhs_max;
   c->stream = (hipStream_t)hip_stream;
+  // untuned apply: face data in registers where the kernels have it (the
+  // autotuner may still choose another shape for the FP64 apply)
+  c->tune_apply[0].shape = kset<double>(c).apply_rf ? 2 : 0;
+  c->tune_apply[1].shape = kset<float>(c).apply_rf ? 2 : 0;
   std::vector<unsigned char> t64, t32;
   fill_tab_k<double>(c->k, c->host, t64);
   fill_tab_k<float>(c->k, c->host, t32);

@@ -693,6 +693,33 @@ __device__ __forceinline__ void read_xline(const T* __restrict__ x, long long ro
   }
 }
 
+// Lines of a patch within one wave (3-D Q1, Q3: TPP = 16 or 64 lanes): values
+// held one per lane can be contracted across lanes.
+constexpr bool kZShfl = (TPP <= 64) && (64 % TPP == 0);
+
+// row[nu] = M[mu][nu] for a lane-dependent mu
+template <typename T>
+__device__ __forceinline__ void mass_row(int mu, T (&row)[n]) {
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) {
+    T v = T(kRef.M[nu]);
+#pragma unroll
+    for (int m = 1; m < n; ++m)
+      if (mu == m) v = T(kRef.M[m * n + nu]);
+    row[nu] = v;
+  }
+}
+
+// sum_nu row[nu] v(lane + E (nu - mu)): the y-contraction of z-face values
+// held one per lane (wl: the lane's index in its wave)
+template <typename T>
+__device__ __forceinline__ T ycontract_lanes(const T (&row)[n], T v, int wl, int mu) {
+  T s = T(0);
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) s += row[nu] * __shfl(v, wl + E * (nu - mu), 64);
+  return s;
+}
+
 // Operator passes of y = A_ref x on the patch.  Phase X0 reads the x-lines
 // from global (and keeps them in xl for the caller), gathers the y/z face
 // data; the last pass (z in 3-D, y in 2-D) hands each output line to
@@ -703,6 +730,13 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
                                                 int lane, bool active, Line<T>& xl,
                                                 const Sides<T>& ysd_global, Emit emit) {
   constexpr int NCOMP = (MODE == 0) ? 2 : 1;
+  // Dirichlet smoothers on patches of one wave: the z-face traces go through
+  // registers, not LDS.  Lane (px, py) reads the n traces of its x-block on
+  // each z-neighbour and contracts beta = -+t/2 with its mass row (as
+  // gather_ext + extz_mass_x_line), the Z pass contracts along y across lanes
+  // (as ext_my): the same values, no extra pass over the face arrays.
+  constexpr bool RFZ = (D == 3) && kZShfl && (MODE == 1 || MODE == 2);
+  T wz0 = T(0), wz1 = T(0);
   // the smoothers' residual is only used on V_j: along each direction the two
   // tile ends are skipped unless they lie on the domain boundary (outputs left
   // at the ends are never read by a used result)
@@ -711,7 +745,32 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
   const bool n0z = MODE == 0 || (P.ty[2] & 1), nEz = MODE == 0 || (P.ty[2] & 2);
   // X0: a = M_x x -> A, b = L_x x -> B
   if (active) {
-    gather_ext<T, MODE>(t, x, N, P, lane, ext);
+    if constexpr (RFZ) {
+      if constexpr (MODE == 1) {
+        const int px = lane % E, q = lane / E;
+        T rowx[n];
+        mass_row<T>(px % n, rowx);
+        const T half = T(0.5);
+        const int cx = P.lo[0] + px / n, cy = P.lo[1] + q / n;
+        const long long o = (long long)n * (q % n);
+        if (P.lo[2] > 0) {
+          const T* c = x + cell_index(N, cx, cy, P.lo[2] - 1) * NC + o + K * n * n;
+          T s = T(0);
+#pragma unroll
+          for (int nu = 0; nu < n; ++nu) s += rowx[nu] * (-half * c[nu]);
+          wz0 = s;
+        }
+        if (P.lo[2] + 2 < N) {
+          const T* c = x + cell_index(N, cx, cy, P.lo[2] + 2) * NC + o;
+          T s = T(0);
+#pragma unroll
+          for (int nu = 0; nu < n; ++nu) s += rowx[nu] * (half * c[nu]);
+          wz1 = s;
+        }
+      }
+    } else {
+      gather_ext<T, MODE>(t, x, N, P, lane, ext);
+    }
     for (int i = lane; i < NL; i += TPP) {
       const int py = i % E, pz = i / E;
       const long long row0 = xrow_offset(N, P, py, pz);
@@ -730,7 +789,7 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
   if constexpr (D == 3) {
     // Y: c = M_y b + L_y a -> B, d = M_y a -> A; z-face data contracted along x
     if (active) {
-      for (int i = lane; i < NL + 2 * NCOMP * E; i += TPP) {
+      for (int i = lane; i < NL + (RFZ ? 0 : 2 * NCOMP * E); i += TPP) {
         if (i < NL) {
           const int px = i % E, pz = i / E;
           int base, stride;
@@ -759,7 +818,23 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
         Line<T> c, d, y;
         load_line(B, base, stride, c);
         load_line(A, base, stride, d);
-        Sides<T> sd = zline_sides<T, NCOMP>(t, ext, N, P, px, py);
+        Sides<T> sd;
+        if constexpr (RFZ) {
+          sd.bl = (P.lo[2] == 0);
+          sd.br = (P.lo[2] + 1 == N - 1);
+          sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+          if constexpr (MODE == 1) {
+            T rowy[n];
+            mass_row<T>(py % n, rowy);
+            const int wl = threadIdx.x & 63;
+            const T zL = ycontract_lanes<T>(rowy, wz0, wl, py % n);
+            const T zR = ycontract_lanes<T>(rowy, wz1, wl, py % n);
+            if (!sd.bl) sd.bL = zL;
+            if (!sd.br) sd.bR = zR;
+          }
+        } else {
+          sd = zline_sides<T, NCOMP>(t, ext, N, P, px, py);
+        }
         sd.lit = (MODE == 2);
         line_mass<T>(t, c, y, n0z, nEz);
         line_sipg<T, true>(t, d, sd, y, n0z, nEz);
@@ -864,20 +939,6 @@ k_apply(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restri
 // 4 E^2 values elsewhere (Q7 in FP64: 78 KB instead of 86 KB, two patches per
 // CU instead of one).
 constexpr bool kApplyRF = (D == 3);
-constexpr bool kZShfl = (TPP <= 64) && (64 % TPP == 0);
-
-// row[nu] = M[mu][nu] for a lane-dependent mu
-template <typename T>
-__device__ __forceinline__ void mass_row(int mu, T (&row)[n]) {
-#pragma unroll
-  for (int nu = 0; nu < n; ++nu) {
-    T v = T(kRef.M[nu]);
-#pragma unroll
-    for (int m = 1; m < n; ++m)
-      if (mu == m) v = T(kRef.M[m * n + nu]);
-    row[nu] = v;
-  }
-}
 
 // Couplings of the n face nodes nu of an x-block of a neighbour cell across
 // a y- or z-face (SIDE 0: the neighbour below, read at its far end; SIDE 1:
@@ -912,16 +973,6 @@ __device__ __forceinline__ void face_pair(const Tab<K, T>* __restrict__ t, const
   for (int nu = 0; nu < n; ++nu) sb += row[nu] * be[nu];
   a = sa;
   b = sb;
-}
-
-// sum_nu row[nu] v(lane + E (nu - mu)): the y-contraction of z-face values
-// held one per lane
-template <typename T>
-__device__ __forceinline__ T ycontract_lanes(const T (&row)[n], T v, int wl, int mu) {
-  T s = T(0);
-#pragma unroll
-  for (int nu = 0; nu < n; ++nu) s += row[nu] * __shfl(v, wl + E * (nu - mu), 64);
-  return s;
 }
 
 template <typename T, int PPB>
