@@ -720,6 +720,57 @@ __device__ __forceinline__ T ycontract_lanes(const T (&row)[n], T v, int wl, int
   return s;
 }
 
+// Dirichlet smoothers' z-face traces in registers (patches of one wave):
+// lane (px, py) reads the n traces of its x-block on each z-neighbour and
+// contracts beta = -+t/2 with its mass row (the values gather_ext +
+// extz_mass_x_line leave in LDS) ...
+template <typename T>
+__device__ __forceinline__ void rfz_traces(const T* __restrict__ x, int N, const PatchPos& P, int lane,
+                                           T& wz0, T& wz1) {
+  const int px = lane % E, q = lane / E;
+  T rowx[n];
+  mass_row<T>(px % n, rowx);
+  const T half = T(0.5);
+  const int cx = P.lo[0] + px / n, cy = P.lo[1] + q / n;
+  const long long o = (long long)n * (q % n);
+  wz0 = wz1 = T(0);
+  if (P.lo[2] > 0) {
+    const T* c = x + cell_index(N, cx, cy, P.lo[2] - 1) * NC + o + K * n * n;
+    T s = T(0);
+#pragma unroll
+    for (int nu = 0; nu < n; ++nu) s += rowx[nu] * (-half * c[nu]);
+    wz0 = s;
+  }
+  if (P.lo[2] + 2 < N) {
+    const T* c = x + cell_index(N, cx, cy, P.lo[2] + 2) * NC + o;
+    T s = T(0);
+#pragma unroll
+    for (int nu = 0; nu < n; ++nu) s += rowx[nu] * (half * c[nu]);
+    wz1 = s;
+  }
+}
+// ... and the z-line (px, py = lane / E) contracts them along y across lanes
+// (the values zline_sides forms from LDS); TRACES false: no neighbour data
+template <typename T, bool TRACES>
+__device__ __forceinline__ Sides<T> rfz_sides(int N, const PatchPos& P, int lane, T wz0, T wz1) {
+  Sides<T> sd;
+  sd.bl = (P.lo[2] == 0);
+  sd.br = (P.lo[2] + 1 == N - 1);
+  sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  sd.lit = false;
+  if constexpr (TRACES) {
+    const int py = lane / E;
+    T rowy[n];
+    mass_row<T>(py % n, rowy);
+    const int wl = threadIdx.x & 63;
+    const T zL = ycontract_lanes<T>(rowy, wz0, wl, py % n);
+    const T zR = ycontract_lanes<T>(rowy, wz1, wl, py % n);
+    if (!sd.bl) sd.bL = zL;
+    if (!sd.br) sd.bR = zR;
+  }
+  return sd;
+}
+
 // Operator passes of y = A_ref x on the patch.  Phase X0 reads the x-lines
 // from global (and keeps them in xl for the caller), gathers the y/z face
 // data; the last pass (z in 3-D, y in 2-D) hands each output line to
@@ -746,28 +797,7 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
   // X0: a = M_x x -> A, b = L_x x -> B
   if (active) {
     if constexpr (RFZ) {
-      if constexpr (MODE == 1) {
-        const int px = lane % E, q = lane / E;
-        T rowx[n];
-        mass_row<T>(px % n, rowx);
-        const T half = T(0.5);
-        const int cx = P.lo[0] + px / n, cy = P.lo[1] + q / n;
-        const long long o = (long long)n * (q % n);
-        if (P.lo[2] > 0) {
-          const T* c = x + cell_index(N, cx, cy, P.lo[2] - 1) * NC + o + K * n * n;
-          T s = T(0);
-#pragma unroll
-          for (int nu = 0; nu < n; ++nu) s += rowx[nu] * (-half * c[nu]);
-          wz0 = s;
-        }
-        if (P.lo[2] + 2 < N) {
-          const T* c = x + cell_index(N, cx, cy, P.lo[2] + 2) * NC + o;
-          T s = T(0);
-#pragma unroll
-          for (int nu = 0; nu < n; ++nu) s += rowx[nu] * (half * c[nu]);
-          wz1 = s;
-        }
-      }
+      if constexpr (MODE == 1) rfz_traces<T>(x, N, P, lane, wz0, wz1);
     } else {
       gather_ext<T, MODE>(t, x, N, P, lane, ext);
     }
@@ -819,22 +849,8 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
         load_line(B, base, stride, c);
         load_line(A, base, stride, d);
         Sides<T> sd;
-        if constexpr (RFZ) {
-          sd.bl = (P.lo[2] == 0);
-          sd.br = (P.lo[2] + 1 == N - 1);
-          sd.aL = sd.bL = sd.aR = sd.bR = T(0);
-          if constexpr (MODE == 1) {
-            T rowy[n];
-            mass_row<T>(py % n, rowy);
-            const int wl = threadIdx.x & 63;
-            const T zL = ycontract_lanes<T>(rowy, wz0, wl, py % n);
-            const T zR = ycontract_lanes<T>(rowy, wz1, wl, py % n);
-            if (!sd.bl) sd.bL = zL;
-            if (!sd.br) sd.bR = zR;
-          }
-        } else {
-          sd = zline_sides<T, NCOMP>(t, ext, N, P, px, py);
-        }
+        if constexpr (RFZ) sd = rfz_sides<T, MODE == 1>(N, P, i, wz0, wz1);
+        else sd = zline_sides<T, NCOMP>(t, ext, N, P, px, py);
         sd.lit = (MODE == 2);
         line_mass<T>(t, c, y, n0z, nEz);
         line_sipg<T, true>(t, d, sd, y, n0z, nEz);
@@ -1641,7 +1657,8 @@ __device__ __forceinline__ void smooth_split_body(const Tab<K, T>* __restrict__ 
     const Sides<T> ysd = active ? yline_sides_global<T, OPM>(t, xr, g.N, P, lane % E, lane / E) : Sides<T>{};
     // X0: a = M_x x, b = L_x x on this half -> A, B
     if (active) {
-      // z-face traces, spread over both waves
+      // z-face traces, spread over both waves (the register form of the
+      // one-wave kernel measured slower here: both waves would repeat it)
       for (int i = lane + H * TPP; i < 2 * NF; i += 2 * TPP) {
         const int f = i % NF;
         const int side = i / NF;
