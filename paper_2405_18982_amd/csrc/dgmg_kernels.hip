@@ -720,6 +720,41 @@ __device__ __forceinline__ T ycontract_lanes(const T (&row)[n], T v, int wl, int
   return s;
 }
 
+// Couplings of the n face nodes nu of an x-block of a neighbour cell across
+// a y- or z-face (SIDE 0: the neighbour below, read at its far end; SIDE 1:
+// above, read at its near end); node nu, normal index j sits at
+// c[nu + j strideN].  a = sum_nu row[nu] alpha(nu), b = sum_nu row[nu] beta(nu).
+template <typename T, int SIDE>
+__device__ __forceinline__ void face_pair(const Tab<K, T>* __restrict__ t, const T* __restrict__ c,
+                                          int strideN, const T (&row)[n], T& a, T& b) {
+  const T half = T(0.5);
+  const T sg = t->sigma;
+  // row by row along the normal (n accumulators live, not n^2 values)
+  T g[n], tr[n], al[n], be[n];
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) g[nu] = T(0);
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int nu = 0; nu < n; ++nu) {
+      const T v = c[nu + j * strideN];
+      g[nu] += (SIDE == 0 ? T(kRef.d1[j]) : T(kRef.d0[j])) * v;
+      if (j == (SIDE == 0 ? K : 0)) tr[nu] = v;
+    }
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) {
+    al[nu] = (SIDE == 0) ? (half * g[nu] - sg * tr[nu]) : (-sg * tr[nu] - half * g[nu]);
+    be[nu] = (SIDE == 0) ? -half * tr[nu] : half * tr[nu];
+  }
+  T sa = T(0), sb = T(0);
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) sa += row[nu] * al[nu];
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) sb += row[nu] * be[nu];
+  a = sa;
+  b = sb;
+}
+
 // Dirichlet smoothers' z-face traces in registers (patches of one wave):
 // lane (px, py) reads the n traces of its x-block on each z-neighbour and
 // contracts beta = -+t/2 with its mass row (the values gather_ext +
@@ -775,7 +810,9 @@ __device__ __forceinline__ Sides<T> rfz_sides(int N, const PatchPos& P, int lane
 // from global (and keeps them in xl for the caller), gathers the y/z face
 // data; the last pass (z in 3-D, y in 2-D) hands each output line to
 // emit(line, base, stride, y).  A, B: LDS tiles; ext: LDS face data.
-template <typename T, int MODE, typename Emit>
+// RFA (operator data, patches of one wave): the y- and z-neighbour face data
+// in registers and across lanes as in k_apply_rf instead of the LDS arrays.
+template <typename T, int MODE, bool RFA = false, typename Emit>
 __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t, const T* __restrict__ x,
                                                 int N, const PatchPos& P, T* A, T* B, T* ext,
                                                 int lane, bool active, Line<T>& xl,
@@ -787,7 +824,10 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
   // gather_ext + extz_mass_x_line), the Z pass contracts along y across lanes
   // (as ext_my): the same values, no extra pass over the face arrays.
   constexpr bool RFZ = (D == 3) && kZShfl && (MODE == 1 || MODE == 2);
+  static_assert(!RFA || (MODE == 0 && D == 3 && kZShfl), "register face data: 3-D operator, one wave");
   T wz0 = T(0), wz1 = T(0);
+  T ya0 = T(0), yb0 = T(0), ya1 = T(0), yb1 = T(0);  // RFA: y-line (px, pz) = (lane % E, lane / E)
+  T za0 = T(0), zb0 = T(0), za1 = T(0), zb1 = T(0);  // RFA: z-face node (px, py) = (lane % E, lane / E)
   // the smoothers' residual is only used on V_j: along each direction the two
   // tile ends are skipped unless they lie on the domain boundary (outputs left
   // at the ends are never read by a used result)
@@ -798,6 +838,17 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
   if (active) {
     if constexpr (RFZ) {
       if constexpr (MODE == 1) rfz_traces<T>(x, N, P, lane, wz0, wz1);
+    } else if constexpr (RFA) {
+      const int px = lane % E, q = lane / E;
+      T rowx[n];
+      mass_row<T>(px % n, rowx);
+      const int cx = P.lo[0] + px / n;
+      const long long oy = (long long)(n * n) * (q % n), oz = (long long)n * (q % n);
+      const int cz = P.lo[2] + q / n, cy = P.lo[1] + q / n;
+      if (P.lo[1] > 0) face_pair<T, 0>(t, x + cell_index(N, cx, P.lo[1] - 1, cz) * NC + oy, n, rowx, ya0, yb0);
+      if (P.lo[1] + 2 < N) face_pair<T, 1>(t, x + cell_index(N, cx, P.lo[1] + 2, cz) * NC + oy, n, rowx, ya1, yb1);
+      if (P.lo[2] > 0) face_pair<T, 0>(t, x + cell_index(N, cx, cy, P.lo[2] - 1) * NC + oz, n * n, rowx, za0, zb0);
+      if (P.lo[2] + 2 < N) face_pair<T, 1>(t, x + cell_index(N, cx, cy, P.lo[2] + 2) * NC + oz, n * n, rowx, za1, zb1);
     } else {
       gather_ext<T, MODE>(t, x, N, P, lane, ext);
     }
@@ -819,7 +870,7 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
   if constexpr (D == 3) {
     // Y: c = M_y b + L_y a -> B, d = M_y a -> A; z-face data contracted along x
     if (active) {
-      for (int i = lane; i < NL + (RFZ ? 0 : 2 * NCOMP * E); i += TPP) {
+      for (int i = lane; i < NL + ((RFZ || RFA) ? 0 : 2 * NCOMP * E); i += TPP) {
         if (i < NL) {
           const int px = i % E, pz = i / E;
           int base, stride;
@@ -827,7 +878,18 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
           Line<T> a, b, c, d;
           load_line(A, base, stride, a);
           load_line(B, base, stride, b);
-          const Sides<T> sd = (MODE == 0) ? yline_sides<T, NCOMP>(t, ext, N, P, px, pz) : ysd_global;
+          Sides<T> sd;
+          if constexpr (RFA) {
+            sd.bl = (P.lo[1] == 0);
+            sd.br = (P.lo[1] + 1 == N - 1);
+            sd.aL = ya0;
+            sd.bL = yb0;
+            sd.aR = ya1;
+            sd.bR = yb1;
+            sd.lit = false;
+          } else {
+            sd = (MODE == 0) ? yline_sides<T, NCOMP>(t, ext, N, P, px, pz) : ysd_global;
+          }
           line_mass<T>(t, b, c, n0y, nEy);
           line_sipg<T, true>(t, a, sd, c, n0y, nEy);
           line_mass<T>(t, a, d, n0y, nEy);
@@ -849,8 +911,26 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
         load_line(B, base, stride, c);
         load_line(A, base, stride, d);
         Sides<T> sd;
-        if constexpr (RFZ) sd = rfz_sides<T, MODE == 1>(N, P, i, wz0, wz1);
-        else sd = zline_sides<T, NCOMP>(t, ext, N, P, px, py);
+        if constexpr (RFZ) {
+          sd = rfz_sides<T, MODE == 1>(N, P, i, wz0, wz1);
+        } else if constexpr (RFA) {
+          T rowy[n];
+          mass_row<T>(py % n, rowy);
+          const int wl = threadIdx.x & 63;
+          const T zaL = ycontract_lanes<T>(rowy, za0, wl, py % n);
+          const T zbL = ycontract_lanes<T>(rowy, zb0, wl, py % n);
+          const T zaR = ycontract_lanes<T>(rowy, za1, wl, py % n);
+          const T zbR = ycontract_lanes<T>(rowy, zb1, wl, py % n);
+          sd.bl = (P.lo[2] == 0);
+          sd.br = (P.lo[2] + 1 == N - 1);
+          sd.aL = sd.bl ? T(0) : zaL;
+          sd.bL = sd.bl ? T(0) : zbL;
+          sd.aR = sd.br ? T(0) : zaR;
+          sd.bR = sd.br ? T(0) : zbR;
+          sd.lit = false;
+        } else {
+          sd = zline_sides<T, NCOMP>(t, ext, N, P, px, py);
+        }
         sd.lit = (MODE == 2);
         line_mass<T>(t, c, y, n0z, nEz);
         line_sipg<T, true>(t, d, sd, y, n0z, nEz);
@@ -955,41 +1035,6 @@ k_apply(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restri
 // 4 E^2 values elsewhere (Q7 in FP64: 78 KB instead of 86 KB, two patches per
 // CU instead of one).
 constexpr bool kApplyRF = (D == 3);
-
-// Couplings of the n face nodes nu of an x-block of a neighbour cell across
-// a y- or z-face (SIDE 0: the neighbour below, read at its far end; SIDE 1:
-// above, read at its near end); node nu, normal index j sits at
-// c[nu + j strideN].  a = sum_nu row[nu] alpha(nu), b = sum_nu row[nu] beta(nu).
-template <typename T, int SIDE>
-__device__ __forceinline__ void face_pair(const Tab<K, T>* __restrict__ t, const T* __restrict__ c,
-                                          int strideN, const T (&row)[n], T& a, T& b) {
-  const T half = T(0.5);
-  const T sg = t->sigma;
-  // row by row along the normal (n accumulators live, not n^2 values)
-  T g[n], tr[n], al[n], be[n];
-#pragma unroll
-  for (int nu = 0; nu < n; ++nu) g[nu] = T(0);
-#pragma unroll
-  for (int j = 0; j < n; ++j)
-#pragma unroll
-    for (int nu = 0; nu < n; ++nu) {
-      const T v = c[nu + j * strideN];
-      g[nu] += (SIDE == 0 ? T(kRef.d1[j]) : T(kRef.d0[j])) * v;
-      if (j == (SIDE == 0 ? K : 0)) tr[nu] = v;
-    }
-#pragma unroll
-  for (int nu = 0; nu < n; ++nu) {
-    al[nu] = (SIDE == 0) ? (half * g[nu] - sg * tr[nu]) : (-sg * tr[nu] - half * g[nu]);
-    be[nu] = (SIDE == 0) ? -half * tr[nu] : half * tr[nu];
-  }
-  T sa = T(0), sb = T(0);
-#pragma unroll
-  for (int nu = 0; nu < n; ++nu) sa += row[nu] * al[nu];
-#pragma unroll
-  for (int nu = 0; nu < n; ++nu) sb += row[nu] * be[nu];
-  a = sa;
-  b = sb;
-}
 
 template <typename T, int PPB>
 __global__ void __launch_bounds__(TPP * PPB)
@@ -1843,7 +1888,10 @@ k_smooth_split(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scal
 // bc = P^T (b - A x): the colour-0 patch of level l is the set of children of
 // one coarse cell, so its residual contracts with the stacked P^T per
 // direction straight into that coarse cell.
-constexpr int kRestrictPP = Smem<2, (D - 1) * 2 * 2 * NF>::per_patch;
+// Q1, Q3 in 3-D: the operator pass takes the neighbour face data in registers
+// (as the apply's shape 2): two tiles of LDS per patch, no face arrays.
+constexpr bool kRestrictRF = (D == 3) && kZShfl;
+constexpr int kRestrictPP = kRestrictRF ? 2 * TS : Smem<2, (D - 1) * 2 * 2 * NF>::per_patch;
 
 template <typename T>
 __device__ __forceinline__ void restrict_body(const Tab<K, T>* __restrict__ t, const PatchGrid& g, T scale,
@@ -1858,7 +1906,7 @@ __device__ __forceinline__ void restrict_body(const Tab<K, T>* __restrict__ t, c
   const PatchPos P = patch_pos(g, active ? pid : 0);
   Line<T> xl;
   Sides<T> ysd{};
-  operator_passes<T, 0>(t, x + roff, g.N, P, A, B, ext, lane, active, xl, ysd,
+  operator_passes<T, 0, kRestrictRF>(t, x + roff, g.N, P, A, B, ext, lane, active, xl, ysd,
                         [&](int l, int base, int stride, const Line<T>& v) {
                           Line<T> r;
                           read_lastline<T>(b + roff, g.N, P, l, r);
