@@ -174,6 +174,41 @@ def bench_batched(reps=3):
     return out
 
 
+def bench_adjoint(reps=3):
+    """2-D Q5 256^2 (2.4M DoFs), kappa = 1: the differentiable solve, loss
+    1/2 |u - u_t|^2 with load and target interpolated from seeded Fourier
+    fields; forward solve and backward (adjoint solve + dL/dkappa) timed
+    separately, tolerance 1e-10."""
+    import torch
+    from paper_2405_18982_amd import dgmg, inputs
+    w = inputs.WORKLOADS["poisson2d_q5_256c_adjoint"]
+    prob = dgmg.Problem(w["dim"], w["k"], w["L"], kappa=w["kappa"])
+    prob.autotune(nrhs=1)
+    X = prob.node_coords()
+    b = prob.mass(torch.from_numpy(inputs.fourier_field(inputs.fourier_modes(w["seed"]), X)).cuda())
+    ut = torch.from_numpy(inputs.fourier_field(inputs.fourier_modes(w["target_seed"]), X)).cuda()
+    tf = tb = 0.0
+    for rep in range(reps + 1):
+        bb = b.clone().requires_grad_(True)
+        kap = torch.tensor(w["kappa"], dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = dgmg.solve(bb, kap, prob, rtol=1e-10)
+        loss = 0.5 * ((u - ut) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rep > 0:  # the first pass warms up
+            tf += t1 - t0
+            tb += t2 - t1
+    out = {"ndofs": prob.ndofs(), "forward_ms": tf / reps * 1e3, "backward_ms": tb / reps * 1e3,
+           "dloss_dkappa": float(kap.grad), "grad_b_norm": float(torch.linalg.norm(bb.grad))}
+    prob.close()
+    return out
+
+
 def bench_full_kernel(b, xin, t_smooth_dirichlet, ms_dirichlet, reps=5):
     """The Full vertex-patch kernel (whole patch, residual once per colour) on
     the bench workload: smoothing-step time against the Dirichlet kernel's
@@ -208,7 +243,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 3-D Q7 mixed and the batched 16-RHS time-to-solution runs")
+                    help="skip the 3-D Q7 mixed, the batched 16-RHS and the 2-D adjoint runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU slab decomposition is "
@@ -334,6 +369,7 @@ def main():
         components["full_kernel"] = bench_full_kernel(b, xin, t_smooth, ms)
         components["q7_64c_fp64_vs_mixed"] = bench_q7_mixed()
         components["q4_32c_16rhs_batched"] = bench_batched()
+        components["q5_256c_2d_adjoint"] = bench_adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dim, k, L, sigma, iters)
     prob.close()
