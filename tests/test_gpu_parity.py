@@ -246,6 +246,30 @@ def test_pcg_batched_equals_single():
         assert rel[j] <= 1e-10
 
 
+@pytest.mark.parametrize("precision", [64, 32])
+def test_pcg_batched_masks_match_single_solves(precision):
+    """Right-hand sides that stop at different iterations in one batched
+    solve (a zero one stops before the first, a smooth one early): the
+    device-side convergence mask freezes each at its own iteration, with the
+    single solve's iteration count, residual and solution."""
+    note(f"pcg batched masks fp{precision}")
+    dim, k, L = 3, 3, 2
+    prob = problem(dim, k, L, precision=precision, nrhs_max=4)
+    n = prob.ndofs()
+    B = inputs.normal(23, (4, n))
+    B[1] = 0.0
+    B[3] = host(prob.mass(cuda(inputs.sine_load(prob.node_coords()))))
+    X, it, rel = prob.solve(cuda(B), rtol=1e-10)
+    X = host(X)
+    assert int(it[1]) == 0 and np.all(X[1] == 0.0)
+    assert len({int(v) for v in it}) > 1
+    for j in (0, 2, 3):
+        xj, itj, relj = prob.solve(cuda(B[j]), rtol=1e-10)
+        assert int(itj[0]) == int(it[j])
+        assert rel[j] <= 1e-10 and abs(float(relj[0]) - float(rel[j])) <= 1e-6 * float(rel[j])
+        close(X[j], host(xj), rtol=1e-13, mtol=1e-12)
+
+
 def test_repeatable_bitwise():
     note("determinism")
     prob = problem(3, 3, 2)
