@@ -246,8 +246,8 @@ def main():
                     help="skip the 3-D Q7 mixed, the batched 16-RHS and the 2-D adjoint runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU slab decomposition is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print("bench.py: the library runs on one GPU only (--gpus 1); it has no multi-GPU "
+              "path", file=sys.stderr)
         sys.exit(2)
 
     import torch
