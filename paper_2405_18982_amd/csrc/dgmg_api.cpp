@@ -133,7 +133,7 @@ struct dgmg_ctx {
   double* hbuf = nullptr;  // pinned host mirror of scalars
   int* hact = nullptr;
   // CG convergence decided on the device: norms of b (device, uploaded from
-  // the pinned hnb once per solve), the update kernel's record (pinned host
+  // the pinned hnb once per solve), the check kernel's record (pinned host
   // memory, 4 doubles per right-hand side; rec_dev is its device address) and
   // the event the host waits on by polling
   double* nb = nullptr;
