@@ -1098,8 +1098,8 @@ template <typename T>
 dgmg_status tune_kernel(dgmg_ctx* c, int nrhs, bool smooth, int level, T* x, T* y,
                         dgmg_ctx::Tuning& slot) {
   int nshapes = smooth ? dgmg::kSmoothShapes : dgmg::kApplyShapes;
-  if (smooth && (!kset<T>(c).smooth_split || c->variant == DGMG_SMOOTH_FULL))
-    nshapes = dgmg::kSmoothShapes / 2;  // the two-wave shapes would repeat the others
+  if (smooth && !(c->variant == DGMG_SMOOTH_FULL ? kset<T>(c).smooth_hi_full : kset<T>(c).smooth_split))
+    nshapes = dgmg::kSmoothShapes / 2;  // shapes 4..7 would repeat the others
   if (!smooth && !kset<T>(c).apply_rf) nshapes = 2;  // shape 2 would repeat shape 0
   const int reps = smooth ? 3 : 20;
   hipEvent_t e0, e1;
