@@ -9,7 +9,7 @@ namespace dgmg {
 
 constexpr int kMaxDegree = 7;
 constexpr int kApplyShapes = 3;   // workgroup shapes of apply (2: face data in registers)
-constexpr int kSmoothShapes = 8;  // workgroup shape x prefetch of b x (3-D) two waves per patch / (2-D) one patch per workgroup
+constexpr int kSmoothShapes = 8;  // workgroup shape x prefetch of b x two waves per patch / one patch per workgroup
 
 // Reference (h = 1, kappa = 1) data of Q_K on a two-cell patch that depends
 // on the penalty, in the arithmetic type T of the kernels that read them.
@@ -66,8 +66,9 @@ struct KernelSet {
   hipError_t (*smooth[kSmoothShapes])(const void* tab, PatchGrid g, T scale, T inv_scale, int variant,
                           int zero, const T* xin, T* xout, const T* b, int nrhs, long long ndof,
                           hipStream_t s);
-  // 1 where shapes 4..7 (3-D: two waves per patch; 2-D: one patch per
-  // workgroup) differ from 0..3; smooth_hi_full: also for the Full kernel
+  // 1 where shapes 4..7 (two waves per patch, or one patch per workgroup
+  // where patches share a wave) differ from 0..3; smooth_hi_full: also for
+  // the Full kernel
   int smooth_split;
   int smooth_hi_full;
   hipError_t (*restrict_residual)(const void* tab, PatchGrid g, T scale, const T* x, const T* b,

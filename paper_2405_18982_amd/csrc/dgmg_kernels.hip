@@ -2289,15 +2289,16 @@ hipError_t launch_mass(const void* tab, PatchGrid g, T scale, const T* x, T* y, 
   return hipGetLastError();
 }
 // smoother shapes: bit 0 selects the workgroup shape, bit 1 the prefetch of b,
-// bit 2 two waves per patch in 3-D (where kSplitOK; otherwise the same as bit 2
-// clear) and one patch per workgroup in 2-D (several 2-D patches share a wave,
-// and patches of different types there run their fast-diagonalisation
-// branches one after the other); variant 0 / 1 / 2 / 3: Dirichlet consistent /
-// Dirichlet with the paper's residual / Full / clamped
+// bit 2 two waves per patch where kSplitOK, else one patch per workgroup where
+// several patches share a wave (2-D, 3-D Q1: patches of different types there
+// run their fast-diagonalisation branches one after the other), else the same
+// as bit 2 clear; variant 0 / 1 / 2 / 3: Dirichlet consistent / Dirichlet with
+// the paper's residual / Full / clamped
+constexpr bool kOnePatchShape = !kSplitOK && PPB_DEFAULT > 1;
 template <typename T, int V>
 hipError_t launch_smooth(const void* tab, PatchGrid g, T scale, T inv_scale, int variant, int zero,
                          const T* xin, T* xout, const T* b, int nrhs, long long ndof, hipStream_t s) {
-  constexpr int PPB = (D == 2 && (V & 4)) ? 1 : Shape<(V & 1)>::PPB;
+  constexpr int PPB = (kOnePatchShape && (V & 4)) ? 1 : Shape<(V & 1)>::PPB;
   constexpr bool PF = (V & 2) != 0;
   constexpr bool SPLIT = (V & 4) != 0 && kSplitOK;
   dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
@@ -2430,8 +2431,8 @@ KernelSet<T> make_set() {
   k.smooth[5] = &launch_smooth<T, 5>;
   k.smooth[6] = &launch_smooth<T, 6>;
   k.smooth[7] = &launch_smooth<T, 7>;
-  k.smooth_split = (kSplitOK || D == 2) ? 1 : 0;
-  k.smooth_hi_full = (D == 2) ? 1 : 0;
+  k.smooth_split = (kSplitOK || kOnePatchShape) ? 1 : 0;
+  k.smooth_hi_full = kOnePatchShape ? 1 : 0;
   k.restrict_residual = &launch_restrict<T>;
   k.prolongate_add = &launch_prolong<T>;
   k.coarse = &launch_coarse<T>;
