@@ -697,17 +697,25 @@ __device__ __forceinline__ void read_xline(const T* __restrict__ x, long long ro
 // held one per lane can be contracted across lanes.
 constexpr bool kZShfl = (TPP <= 64) && (64 % TPP == 0);
 
-// row[nu] = M[mu][nu] for a lane-dependent mu
+// row[nu] = M[mu][nu] for a lane-dependent mu, read from a device copy of
+// the mass matrix (n vector loads instead of a select chain per entry)
+template <typename T>
+struct MassRows {
+  T v[n * n];
+};
+template <typename T>
+constexpr MassRows<T> make_mass_rows() {
+  MassRows<T> r{};
+  for (int i = 0; i < n * n; ++i) r.v[i] = T(kRef.M[i]);
+  return r;
+}
+template <typename T>
+__device__ constexpr MassRows<T> kMassRows = make_mass_rows<T>();
+
 template <typename T>
 __device__ __forceinline__ void mass_row(int mu, T (&row)[n]) {
 #pragma unroll
-  for (int nu = 0; nu < n; ++nu) {
-    T v = T(kRef.M[nu]);
-#pragma unroll
-    for (int m = 1; m < n; ++m)
-      if (mu == m) v = T(kRef.M[m * n + nu]);
-    row[nu] = v;
-  }
+  for (int nu = 0; nu < n; ++nu) row[nu] = kMassRows<T>.v[mu * n + nu];
 }
 
 // sum_nu row[nu] v(lane + E (nu - mu)): the y-contraction of z-face values
