@@ -982,7 +982,8 @@ DGMG_API dgmg_status dgmg_gmres_solve(dgmg_ctx* c, const double* b, double* x, d
     HIPCHK(c, dgmg::blas_dot2(c->q, c->q, nullptr, nullptr, n, 1, c->gm_partial, nullptr, nn,
                               nullptr, s));
     HIPCHK(c, hipMemcpyAsync(hh, c->gm_s, sizeof(double) * 3 * (cap + 2), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipEventRecord(c->ev_check, s));
+    RET(poll_event(c, c->ev_check));
     double* Hj = &H[(size_t)j * (maxit + 1)];
     for (int i = 0; i <= j; ++i) Hj[i] = hh[i] + hh[cap + 2 + i];
     const double w2 = hh[2 * (cap + 2)];
@@ -1035,7 +1036,8 @@ DGMG_API dgmg_status dgmg_dot(dgmg_ctx* c, int level, const double* a, const dou
   HIPCHK(c, dgmg::blas_dot2(a, b, nullptr, nullptr, c->lv[level].ndof, nrhs, c->partial, nullptr,
                             res, nullptr, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->hbuf, res, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipEventRecord(c->ev_check, c->stream));
+  RET(poll_event(c, c->ev_check));
   std::memcpy(out, c->hbuf, sizeof(double) * nrhs);
   return DGMG_OK;
 }
