@@ -423,14 +423,22 @@ dgmg_status vcycle_T(dgmg_ctx* c, const T* bL, T* xL, int nrhs) {
   const int L = c->L;
   auto B = [&](int l) -> const T* { return l == L ? bL : lvb<T>(c->lv[l]); };
   auto X = [&](int l) -> T* { return l == L ? xL : lvx<T>(c->lv[l]); };
-  // levels 1 and 0 in one launch (same arithmetic as the separate kernels)
+  // levels 1 and 0 (2-D: 2, 1 and 0) in one launch (same arithmetic as the
+  // separate kernels)
   const bool fuse = c->fuse_bottom && kset<T>(c).bottom && c->variant != DGMG_SMOOTH_FULL;
-  const int lo = fuse ? 2 : 1;
+  const bool fuse3 = fuse && c->fuse_bottom >= 2 && kset<T>(c).bottom3 && L >= 2;
+  const int lo = fuse3 ? 3 : fuse ? 2 : 1;
   for (int l = L; l >= lo; --l) {
     RET(op_smooth<T>(c, l, X(l), B(l), 0, nrhs, true));
     RET(op_restrict<T>(c, l, X(l), B(l), lvb<T>(c->lv[l - 1]), nrhs));
   }
-  if (fuse) {
+  if (fuse3) {
+    const double s2 = level_scale(c, 2), s1 = level_scale(c, 1);
+    HIPCHK(c, kset<T>(c).bottom3(tab_of<T>(c), c->variant, (T)s2, (T)(1.0 / s2), (T)s1, (T)(1.0 / s1),
+                                 (T)(1.0 / level_scale(c, 0)), X(2), B(2), X(1), lvb<T>(c->lv[1]),
+                                 lvb<T>(c->lv[0]), X(0), nrhs, c->lv[2].ndof, c->lv[1].ndof,
+                                 c->lv[0].ndof, c->stream));
+  } else if (fuse) {
     const double s1 = level_scale(c, 1);
     const int split = (c->fuse_bottom >= 2 && kset<T>(c).bottom_split) ? 1 : 0;
     HIPCHK(c, kset<T>(c).bottom(tab_of<T>(c), c->variant, split, (T)s1, (T)(1.0 / s1),

@@ -86,6 +86,10 @@ struct KernelSet {
                        T* x1, const T* b1, T* b0, T* x0, int nrhs, long long ndof1, long long ndof0,
                        hipStream_t s);
   int bottom_split;
+  // 2-D: levels 2, 1 and 0 in one launch (null where they do not fit)
+  hipError_t (*bottom3)(const void* tab, int variant, T scale2, T inv_scale2, T scale1, T inv_scale1,
+                        T inv_scale0, T* x2, const T* b2, T* x1, T* b1, T* b0, T* x0, int nrhs,
+                        long long ndof2, long long ndof1, long long ndof0, hipStream_t s);
 };
 
 // Registration entry of one kernel translation unit.

@@ -2152,20 +2152,22 @@ constexpr bool bottom_fits() {
   return TPP * kBottomSlots <= 1024 && kBottomSlots * kBottomPP * (int)sizeof(T) <= 160 * 1024;
 }
 
-__device__ __forceinline__ PatchGrid level1_colour(int colour) {
+// the patches of one colour on the level with N cells per direction
+__device__ __forceinline__ PatchGrid level_colour(int N, int colour) {
   PatchGrid g{};
-  g.N = 4;
+  g.N = N;
   g.xcd_remap = 0;
   g.npatch = 1;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const int bit = (i < D) ? (colour >> i) & 1 : 0;
     g.off[i] = bit;
-    g.cnt[i] = (i < D) ? (bit ? 1 : 2) : 1;
+    g.cnt[i] = (i < D) ? (bit ? (N - 2) / 2 : N / 2) : 1;
     g.npatch *= g.cnt[i];
   }
   return g;
 }
+__device__ __forceinline__ PatchGrid level1_colour(int colour) { return level_colour(4, colour); }
 
 template <typename T>
 struct BottomArgs {
@@ -2177,13 +2179,11 @@ struct BottomArgs {
   long long ndof1, ndof0;
 };
 
+// the stages of levels 1 and 0 (patch slot `slot`; slots past a colour's
+// patches only meet the barriers)
 template <typename T, int MODE>
-__global__ void __launch_bounds__(TPP * kBottomSlots)
-k_bottom(const Tab<K, T>* __restrict__ t, BottomArgs<T> a) {
-  __shared__ T smem[kBottomSlots * kBottomPP];
-  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
-  T* sm = smem + slot * kBottomPP;
-  const int rhs = blockIdx.y;
+__device__ __forceinline__ void bottom_body(const Tab<K, T>* __restrict__ t, const BottomArgs<T>& a,
+                                            int slot, int lane, T* sm, int rhs) {
   constexpr int NCOL = 1 << D;
   smooth_body<T, MODE, false, true>(t, level1_colour(0), a.scale1, a.inv_scale1, a.x1, a.x1, a.b1,
                                     a.ndof1, slot, lane, sm, rhs);
@@ -2202,6 +2202,64 @@ k_bottom(const Tab<K, T>* __restrict__ t, BottomArgs<T> a) {
   for (int c = NCOL - 1; c >= 0; --c) {
     smooth_body<T, MODE, false, false>(t, level1_colour(c), a.scale1, a.inv_scale1, a.x1, a.x1, a.b1,
                                        a.ndof1, slot, lane, sm, rhs);
+    __syncthreads();
+  }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TPP * kBottomSlots)
+k_bottom(const Tab<K, T>* __restrict__ t, BottomArgs<T> a) {
+  __shared__ T smem[kBottomSlots * kBottomPP];
+  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  bottom_body<T, MODE>(t, a, slot, lane, smem + slot * kBottomPP, blockIdx.y);
+}
+
+// 2-D: levels 2 (N = 8) to 0 in one workgroup.  A level-2 colour has at most
+// 16 patches (16 slots of E threads), so level 2's smoothing, its restriction
+// and the prolongation back to it join the stages of levels 1 and 0.  Same
+// bodies, so the results equal the separate kernels bit for bit.
+constexpr int kBottom3Slots = 16;
+
+template <typename T>
+constexpr bool bottom3_fits() {
+  return D == 2 && TPP * kBottom3Slots <= 1024 && kBottom3Slots * kBottomPP * (int)sizeof(T) <= 160 * 1024;
+}
+
+template <typename T>
+struct Bottom3Args {
+  BottomArgs<T> a;  // levels 1 and 0 (a.b1 is written here by the level-2 restriction)
+  T scale2, inv_scale2;
+  T* x2;
+  const T* b2;
+  T* b1w;
+  long long ndof2;
+};
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TPP * kBottom3Slots)
+k_bottom3(const Tab<K, T>* __restrict__ t, Bottom3Args<T> a3) {
+  __shared__ T smem[kBottom3Slots * kBottomPP];
+  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  T* sm = smem + slot * kBottomPP;
+  const int rhs = blockIdx.y;
+  constexpr int NCOL = 1 << D;
+  smooth_body<T, MODE, false, true>(t, level_colour(8, 0), a3.scale2, a3.inv_scale2, a3.x2, a3.x2, a3.b2,
+                                    a3.ndof2, slot, lane, sm, rhs);
+  __syncthreads();
+  for (int c = 1; c < NCOL; ++c) {
+    smooth_body<T, MODE, false, false>(t, level_colour(8, c), a3.scale2, a3.inv_scale2, a3.x2, a3.x2,
+                                       a3.b2, a3.ndof2, slot, lane, sm, rhs);
+    __syncthreads();
+  }
+  restrict_body<T>(t, level_colour(8, 0), a3.scale2, a3.x2, a3.b2, a3.b1w, a3.ndof2, a3.a.ndof1, slot, lane,
+                   sm, rhs);
+  __syncthreads();
+  bottom_body<T, MODE>(t, a3.a, slot, lane, sm, rhs);
+  prolong_body<T>(level_colour(8, 0), a3.a.x1, a3.x2, a3.ndof2, a3.a.ndof1, slot, lane, sm, rhs);
+  __syncthreads();
+  for (int c = NCOL - 1; c >= 0; --c) {
+    smooth_body<T, MODE, false, false>(t, level_colour(8, c), a3.scale2, a3.inv_scale2, a3.x2, a3.x2,
+                                       a3.b2, a3.ndof2, slot, lane, sm, rhs);
     __syncthreads();
   }
 }
@@ -2423,6 +2481,32 @@ hipError_t launch_bottom(const void* tab, int variant, int split, T scale1, T in
   }
 }
 
+// levels 2, 1, 0 in one launch (2-D; variants 0 / 1 / 3)
+template <typename T>
+hipError_t launch_bottom3(const void* tab, int variant, T scale2, T inv_scale2, T scale1, T inv_scale1,
+                          T inv_scale0, T* x2, const T* b2, T* x1, T* b1, T* b0, T* x0, int nrhs,
+                          long long ndof2, long long ndof1, long long ndof0, hipStream_t s) {
+  if constexpr (!bottom3_fits<T>()) {
+    return hipErrorInvalidConfiguration;
+  } else {
+    Bottom3Args<T> a3;
+    a3.a = BottomArgs<T>{scale1, inv_scale1, inv_scale0, x1, b1, b0, x0, ndof1, ndof0};
+    a3.scale2 = scale2;
+    a3.inv_scale2 = inv_scale2;
+    a3.x2 = x2;
+    a3.b2 = b2;
+    a3.b1w = b1;
+    a3.ndof2 = ndof2;
+    const Tab<K, T>* tb = (const Tab<K, T>*)tab;
+    const dim3 grid(1, nrhs), block(TPP * kBottom3Slots);
+    if (variant == 0) hipLaunchKernelGGL((k_bottom3<T, 1>), grid, block, 0, s, tb, a3);
+    else if (variant == 1) hipLaunchKernelGGL((k_bottom3<T, 2>), grid, block, 0, s, tb, a3);
+    else if (variant == 3) hipLaunchKernelGGL((k_bottom3<T, 4>), grid, block, 0, s, tb, a3);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+}
+
 template <typename T>
 KernelSet<T> make_set() {
   KernelSet<T> k;
@@ -2446,6 +2530,7 @@ KernelSet<T> make_set() {
   k.coarse = &launch_coarse<T>;
   k.bottom = bottom_fits<T>() ? &launch_bottom<T> : nullptr;
   k.bottom_split = (bottom_fits<T>() && kBottomSplitOK) ? 1 : 0;
+  k.bottom3 = bottom3_fits<T>() ? &launch_bottom3<T> : nullptr;
   return k;
 }
 

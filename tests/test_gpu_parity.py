@@ -350,7 +350,8 @@ def test_graph_replays_equal_eager(precision):
 
 
 @pytest.mark.parametrize("dim,k,L,precision,variant", [
-    (2, 2, 1, 64, 0), (2, 5, 3, 64, 0), (3, 1, 2, 64, 0), (3, 2, 1, 64, 0), (3, 3, 3, 64, 0),
+    (2, 2, 1, 64, 0), (2, 5, 3, 64, 0), (2, 3, 2, 64, 0), (2, 7, 3, 32, 1), (2, 4, 3, 64, 3),
+    (3, 1, 2, 64, 0), (3, 2, 1, 64, 0), (3, 3, 3, 64, 0),
     (3, 3, 2, 32, 0), (3, 4, 2, 32, 0), (3, 3, 2, 64, 1), (3, 3, 2, 64, 3), (3, 4, 1, 64, 0)])
 def test_fused_vcycle_bottom_equals_separate_kernels(monkeypatch, dim, k, L, precision, variant):
     """Levels 1 and 0 in one launch, with one or two waves per patch, give
