@@ -316,6 +316,70 @@ def test_paper_dirichlet_residual_nu_is_level_robust():
     assert abs(nus[0] - nus[1]) <= 0.5, nus
 
 
+def test_golden_tables_are_complete():
+    """Every value printed in Tables 1 and 2 (Sec. 3.3) and in the one-GPU
+    column of Table 4 (Sec. 6) is carried: 30 entries per kernel minus the
+    ones printed as "---"."""
+    assert len(_golden_nu("table1_full_nu.txt")) == 29
+    assert len(_golden_nu("table2_dirichlet_nu.txt")) == 28
+    assert len(_golden_nu("table2_clamped_nu.txt")) == 28
+    t4 = _golden_nu("table4_local_1gpu_nu.txt")
+    assert [L for L, _, _ in t4] == [2, 3, 4, 5, 6, 7] and {k for _, k, _ in t4} == {3}
+
+
+def test_table4_local_kernel_reads_as_the_dirichlet_kernel():
+    """Reading of the undefined "Local" kernel of Table 4 as the Dirichlet
+    kernel: its one-GPU Q3 counts lie within 0.7 of the Dirichlet Q3 column
+    of Table 2 on every level, while the Full (Table 1) and clamped columns
+    lie further away on most levels."""
+    t4 = {L: nu for L, _, nu in _golden_nu("table4_local_1gpu_nu.txt")}
+    dr = {L: nu for L, k, nu in _golden_nu() if k == 3}
+    fu = {L: nu for L, k, nu in _golden_nu("table1_full_nu.txt") if k == 3}
+    cl = {L: nu for L, k, nu in _golden_nu("table2_clamped_nu.txt") if k == 3}
+    for L in t4:
+        assert abs(t4[L] - dr[L]) <= 0.7, L
+        assert abs(t4[L] - dr[L]) < abs(t4[L] - cl[L])
+    assert sum(abs(t4[L] - dr[L]) < abs(t4[L] - fu[L]) for L in t4) >= 5
+
+
+@pytest.mark.slow
+def test_gmres_nu_weak_pin_table4_and_table2_level3():
+    """Dirichlet kernel with the paper's residual, 3-D Q3, paper's penalty:
+    nu at L = 2 within 1.5 of Table 4 (one GPU) and at L = 3 within 1.5 of
+    Table 2."""
+    t4 = {L: nu for L, _, nu in _golden_nu("table4_local_1gpu_nu.txt")}
+    t2 = {(L, k): nu for L, k, nu in _golden_nu()}
+    for L, ref in ((2, t4[2]), (3, t2[(3, 3)])):
+        H = Hierarchy(3, 3, L, 24.0, mode="local")
+        b = load_vector(3, 3, H.N[L], lambda X: np.ones(X.shape[0]))
+        nu = fractional_iterations(gmres(H.apply[L], H.vcycle, b, rtol=1e-8)[2])
+        assert abs(nu - ref) <= 1.5, (L, nu, ref)
+
+
+@pytest.mark.parametrize("precond", ["identity", "vcycle"])
+def test_gmres_solution_and_residual_estimate(precond):
+    """The oracle's GMRES against a direct solve: on 2-D Q2 with 4x4 cells and
+    f = 1 its solution x = sum_i y_i z_i equals the sparse direct solution to
+    1e-9 at rtol 1e-12, and at rtol 1e-6 the Givens residual estimate it
+    returns equals the true relative residual |b - A x|/|b| to 1e-6."""
+    import scipy.sparse.linalg as spla
+    d, k, L = 2, 2, 1
+    H = Hierarchy(d, k, L, sig(k))
+    A = kron_operator(d, k, H.N[L], sig(k)).tocsc()
+    b = load_vector(d, k, H.N[L], lambda X: np.ones(X.shape[0]))
+    M = (lambda v: v.copy()) if precond == "identity" else H.vcycle
+    u = spla.spsolve(A, b)
+    x, m, hist = gmres(H.apply[L], M, b, rtol=1e-12, maxit=A.shape[0])
+    assert hist[-1] <= 1e-12 and m == len(hist) - 1
+    assert np.linalg.norm(x - u) <= 1e-9 * np.linalg.norm(u)
+    x, m, hist = gmres(H.apply[L], M, b, rtol=1e-6, maxit=A.shape[0])
+    true_rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert hist[-1] <= 1e-6 < hist[-2]
+    assert abs(hist[-1] - true_rel) <= 1e-6 * true_rel
+    if precond == "vcycle":
+        assert m <= 8
+
+
 def test_nu_formula_counts_steps():
     # a constant reduction rate of 1e-4 per step needs nu = 2 steps per 8 digits
     hist = [1.0, 1e-4, 1e-8, 1e-12]

@@ -105,6 +105,37 @@ def test_colours_are_race_free(d, k, N):
     assert colour_disjointness(ps)
 
 
+def test_colour_check_catches_a_patch_with_the_wrong_colour():
+    """Planted mistake: a patch next to a colour-0 patch relabelled colour 0.
+    Their Dirichlet write sets share the interior nodes of the common cells,
+    so the race-freedom check must fail."""
+    for d, k, N in [(2, 2, 4), (3, 1, 4)]:
+        ps = PatchSet(d, k, N)
+        j0 = next(j for j, v in enumerate(ps.verts) if all(c == 1 for c in v))
+        nb = next(j for j, v in enumerate(ps.verts)
+                  if v[0] == 2 and all(c == 1 for c in v[1:]))
+        assert ps.colours[j0] == 0 and ps.colours[nb] != 0
+        ps.colours[nb] = 0
+        assert not colour_disjointness(ps)
+
+
+def test_colour_check_catches_a_kept_interior_end_node():
+    """Planted mistake: one interior patch keeps a patch-boundary node on an
+    interior mesh face in its write set.  That node is the face trace that the
+    exact residual of the same-colour patch two cells over reads, so the
+    check must fail; the same patch set without the change passes."""
+    d, k, N = 2, 2, 6
+    ps = PatchSet(d, k, N)
+    assert colour_disjointness(ps)
+    j = next(j for j, v in enumerate(ps.verts) if tuple(v) == (3, 3))
+    E = 2 * (k + 1)
+    m = ps.masks[j].reshape(E, E)  # (y, x) in tile order
+    assert not m[3, E - 1]
+    m[3, E - 1] = True             # the x = right end of a middle tile row
+    ps.masks[j] = m.reshape(ps.masks[j].shape)
+    assert not colour_disjointness(ps)
+
+
 def test_colour0_tiles_mesh_and_dirichlet_sizes():
     # Q3, 3-D: V_j of an interior patch is 6^3, the patch tile 8^3 (Sec. 3.3)
     ps = PatchSet(3, 3, 4)
