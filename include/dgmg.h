@@ -200,10 +200,23 @@ dgmg_status dgmg_gmres_solve(dgmg_ctx* ctx, const double* b, double* x, double r
 
 /* out[j] = a_j . b_j for each right-hand side j (deterministic two-stage
  * reduction); a, b: device [nrhs][ndofs(level)]; out: host [nrhs].  Blocks
- * until the result is on the host.  Used for the coefficient gradient of the
- * differentiable solve (dL/dkappa = -lambda^T A_1 u). */
+ * until the result is on the host. */
 dgmg_status dgmg_dot(dgmg_ctx* ctx, int level, const double* a, const double* b, int nrhs,
                      double* out);
+
+/* Coefficient gradient of the differentiable solve u = A(kappa)^{-1} b with
+ * A(kappa) = kappa A_1 (the adjoint method: for a loss L(u) and the adjoint
+ * solution lambda = A(kappa)^{-1} dL/du, dL/dkappa = -lambda^T A_1 u, since
+ * dA/dkappa = A_1 and the operator is symmetric).  lam, u: device
+ * [nrhs][ndofs(L)] on the finest level.  per_rhs: host [nrhs] receiving
+ * -lambda_j^T A_1 u_j for each right-hand side (may be NULL); total: host,
+ * receiving their sum (in index order), the gradient with respect to the one
+ * coefficient all right-hand sides share.  The operator apply (with kappa = 1),
+ * the inner products, the sign and the sum run on the device; the library's
+ * CG workspace holds A_1 u, so the call must not overlap a solve on the same
+ * context.  Blocks until the values are on the host. */
+dgmg_status dgmg_adjoint_dkappa(dgmg_ctx* ctx, const double* lam, const double* u, int nrhs,
+                                double* per_rhs, double* total);
 
 /* Host-only, no context: the reference (h = 1, kappa = 1) 1-D data of the
  * fast diagonalisation (Sec. 3.2, eq. fast_inverse) for patch type

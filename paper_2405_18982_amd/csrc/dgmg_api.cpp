@@ -138,6 +138,8 @@ struct dgmg_ctx {
   // the event the host waits on by polling
   double* nb = nullptr;
   double* hnb = nullptr;
+  // coefficient gradient per right-hand side and in total (nrhs_max + 1)
+  double* dk = nullptr;
   double* rec = nullptr;
   double* rec_dev = nullptr;
   hipEvent_t ev_check = nullptr;
@@ -290,6 +292,16 @@ dgmg_status op_apply(dgmg_ctx* c, int l, const T* x, T* y, int nrhs) {
   g.xcd_remap = xcd_remap_flag(tu.remap);
   HIPCHK(c, kset<T>(c).apply[tu.shape](tab_of<T>(c), g, (T)level_scale(c, l), x, y, nrhs,
                                        c->lv[l].ndof, c->stream));
+  return DGMG_OK;
+}
+
+// y = A_l(kappa = 1) x: the operator without the coefficient
+dgmg_status op_apply_unit(dgmg_ctx* c, int l, const double* x, double* y, int nrhs) {
+  const auto& tu = c->tune_apply[0];
+  PatchGrid g = grid_colour0(c, c->lv[l].N);
+  g.xcd_remap = xcd_remap_flag(tu.remap);
+  const double sc = std::pow(c->lv[l].h, c->dim - 2);
+  HIPCHK(c, kset<double>(c).apply[tu.shape](c->tab64, g, sc, x, y, nrhs, c->lv[l].ndof, c->stream));
   return DGMG_OK;
 }
 
@@ -613,6 +625,7 @@ DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int sm
   if (e == hipSuccess) c->partial2 = dalloc<double>((long long)dgmg::kRedBlocks * nrhs_max, e);
   if (e == hipSuccess) c->active = dalloc<int>(nrhs_max, e);
   if (e == hipSuccess) c->nb = dalloc<double>(nrhs_max, e);
+  if (e == hipSuccess) c->dk = dalloc<double>(nrhs_max + 1, e);
   if (e != hipSuccess) return fail(c, DGMG_ERR_ALLOC, "workspace allocation failed");
   HIPCHK(c, hipHostMalloc((void**)&c->hbuf, sizeof(double) * kNumScal * nrhs_max));
   HIPCHK(c, hipHostMalloc((void**)&c->hact, sizeof(int) * nrhs_max));
@@ -1050,6 +1063,25 @@ DGMG_API dgmg_status dgmg_dot(dgmg_ctx* c, int level, const double* a, const dou
   return DGMG_OK;
 }
 
+DGMG_API dgmg_status dgmg_adjoint_dkappa(dgmg_ctx* c, const double* lam, const double* u, int nrhs,
+                                         double* per_rhs, double* total) {
+  RET(check_level(c, c ? c->L : 0, 0, nrhs));
+  if (!lam || !u || !total) return fail(c, DGMG_ERR_ARG, "null argument");
+  const long long n = c->lv[c->L].ndof;
+  // A_1 u in the CG workspace q, first-stage partial sums of lambda . A_1 u,
+  // then the negated sums and their total on the device
+  RET(op_apply_unit(c, c->L, u, c->q, nrhs));
+  HIPCHK(c, dgmg::blas_dot2(lam, c->q, nullptr, nullptr, n, nrhs, c->partial, nullptr, nullptr, nullptr,
+                            c->stream));
+  HIPCHK(c, dgmg::blas_neg_finalize_sum(c->partial, n, nrhs, c->dk, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->hbuf, c->dk, sizeof(double) * (nrhs + 1), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev_check, c->stream));
+  RET(poll_event(c, c->ev_check));
+  if (per_rhs) std::memcpy(per_rhs, c->hbuf, sizeof(double) * nrhs);
+  *total = c->hbuf[nrhs];
+  return DGMG_OK;
+}
+
 namespace {
 
 // ---------------------------------------------------------------- autotuner
@@ -1262,6 +1294,7 @@ DGMG_API dgmg_status dgmg_destroy(dgmg_ctx* c) {
   hipFree(c->partial2);
   hipFree(c->active);
   hipFree(c->nb);
+  hipFree(c->dk);
   free_gmres(c);
   if (c->hbuf) hipHostFree(c->hbuf);
   if (c->hact) hipHostFree(c->hact);

@@ -42,6 +42,12 @@ hipError_t blas_dot2_z32(const double* r, const float* z, const float* zc, const
 hipError_t blas_update_p_z32(double* p, const float* z, const double* rz_part, const double* zq_part,
                              double* rz_new, double* zq, const double* rz_old, const double* alpha,
                              const int* active, int flexible, long long n, int nrhs, hipStream_t s);
+// out[r] = -(sum of the first-stage partial sums blas_dot2 left for vectors
+// of length n), r < nrhs, then out[nrhs] = sum_r out[r] (out: nrhs + 1
+// doubles): the coefficient gradient -lambda^T A_1 u per right-hand side and
+// in total.
+hipError_t blas_neg_finalize_sum(const double* partial, long long n, int nrhs, double* out,
+                                 hipStream_t s);
 // out[i] = V_i . w for the m vectors V_i = V + i n (partial: m * kRedBlocks).
 hipError_t blas_multi_dot(const double* V, const double* w, long long n, int m, double* partial,
                           double* out, hipStream_t s);

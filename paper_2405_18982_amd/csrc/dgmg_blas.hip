@@ -69,6 +69,24 @@ k_finalize(const double* __restrict__ partial, int nblk, double* __restrict__ ou
   if (threadIdx.x == 0) out[blockIdx.x] = r;
 }
 
+// Coefficient gradient of the differentiable solve from the first-stage
+// partial sums of lambda_r . (A_1 u_r): out[r] = -(that sum), summed in the
+// order of k_finalize; then (block 0 of a second launch) out[nrhs] = the sum of
+// out[0..nrhs) in index order, the gradient with respect to one coefficient
+// shared by every right-hand side.
+__global__ void __launch_bounds__(kRedThreads)
+k_neg_finalize(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+  __shared__ double sh[kRedThreads];
+  const double r = sum_partials(partial + blockIdx.x * nblk, nblk, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = -r;
+}
+__global__ void k_sum_rhs(double* __restrict__ out, int nrhs) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int r = 0; r < nrhs; ++r) s += out[r];
+  out[nrhs] = s;
+}
+
 // x += alpha p, r -= alpha q with alpha = rz/pq for active right-hand sides;
 // partial sums of |r|^2.  p^T q comes as the nblk first-stage partial sums of
 // the preceding dot product (pq_part); every block finishes that sum itself
@@ -227,6 +245,13 @@ hipError_t blas_dot2(const double* a, const double* b, const double* c, const do
                      partial2);
   if (out) hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial, g, out);
   if (c && out2) hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial2, g, out2);
+  return hipGetLastError();
+}
+
+hipError_t blas_neg_finalize_sum(const double* partial, long long n, int nrhs, double* out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_neg_finalize, dim3(nrhs), dim3(kRedThreads), 0, s, partial, grid_for(n), out);
+  hipLaunchKernelGGL(k_sum_rhs, dim3(1), dim3(64), 0, s, out, nrhs);
   return hipGetLastError();
 }
 

@@ -50,6 +50,7 @@ SIGNATURES = {
     "dgmg_pcg_solve": (_I, [_P, _P, _P, _I, _D, _I, _I, _P, _P]),
     "dgmg_gmres_solve": (_I, [_P, _P, _P, _D, _I, _P, _P]),
     "dgmg_dot": (_I, [_P, _I, _P, _P, _I, _P]),
+    "dgmg_adjoint_dkappa": (_I, [_P, _P, _P, _I, _P, _P]),
     "dgmg_autotune": (_I, [_P, _I, _c.c_char_p, _P, _I]),
     "dgmg_patch_eigen": (_I, [_I, _D, _I, _I, _P, _P]),
     "dgmg_last_error": (_c.c_char_p, [_P]),
@@ -151,6 +152,14 @@ class Problem:
             raise ValueError(f"tensor size {t.numel()} is not a multiple of ndofs({level}) = {n}")
         return ctypes.c_void_p(t.data_ptr()), t.numel() // n
 
+    def _vec_like(self, t, level, dtype, nrhs, what):
+        """_vec for a secondary tensor, which must hold the same number of
+        right-hand sides as the primary one (checked before any launch)."""
+        ptr, nr = self._vec(t, level, dtype)
+        if nr != nrhs:
+            raise ValueError(f"{what} holds {nr} right-hand side(s), expected {nrhs}")
+        return ptr
+
     def _lvl(self, level):
         return self.L if level is None else level
 
@@ -196,7 +205,7 @@ class Problem:
         f32 = x.dtype == torch.float32
         px, nr = self._vec(x, level, x.dtype)
         out = torch.empty_like(x) if out is None else out
-        py, _ = self._vec(out, level, x.dtype)
+        py = self._vec_like(out, level, x.dtype, nr, "out")
         self._sync_stream()
         fn = lib().dgmg_apply_sipg_f32 if f32 else lib().dgmg_apply_sipg
         self._check(fn(self._ctx, level, px, py, nr))
@@ -207,7 +216,7 @@ class Problem:
         level = self._lvl(level)
         px, nr = self._vec(x, level, torch.float64)
         out = torch.empty_like(x) if out is None else out
-        py, _ = self._vec(out, level, torch.float64)
+        py = self._vec_like(out, level, torch.float64, nr, "out")
         self._sync_stream()
         self._check(lib().dgmg_apply_mass(self._ctx, level, px, py, nr))
         return out
@@ -218,9 +227,7 @@ class Problem:
         level = self._lvl(level)
         f32 = x.dtype == torch.float32
         px, nr = self._vec(x, level, x.dtype)
-        pb, nb = self._vec(b, level, x.dtype)
-        if nb != nr:
-            raise ValueError("x and b differ in nrhs")
+        pb = self._vec_like(b, level, x.dtype, nr, "b")
         self._sync_stream()
         fn = lib().dgmg_smooth_patch_f32 if f32 else lib().dgmg_smooth_patch
         self._check(fn(self._ctx, level, px, pb, int(bool(reverse)), nr))
@@ -231,11 +238,11 @@ class Problem:
         level = self._lvl(level)
         f32 = x.dtype == torch.float32
         px, nr = self._vec(x, level, x.dtype)
-        pb, _ = self._vec(b, level, x.dtype)
+        pb = self._vec_like(b, level, x.dtype, nr, "b")
         if out is None:
             shape = (self.ndofs(level - 1),) if x.dim() == 1 else (nr, self.ndofs(level - 1))
             out = torch.empty(shape, dtype=x.dtype, device=x.device)
-        pc, _ = self._vec(out, level - 1, x.dtype)
+        pc = self._vec_like(out, level - 1, x.dtype, nr, "out")
         self._sync_stream()
         fn = lib().dgmg_restrict_residual_f32 if f32 else lib().dgmg_restrict_residual
         self._check(fn(self._ctx, level, px, pb, pc, nr))
@@ -246,7 +253,7 @@ class Problem:
         level = self._lvl(level)
         f32 = x.dtype == torch.float32
         px, nr = self._vec(x, level, x.dtype)
-        pc, _ = self._vec(xc, level - 1, x.dtype)
+        pc = self._vec_like(xc, level - 1, x.dtype, nr, "xc")
         self._sync_stream()
         fn = lib().dgmg_prolongate_add_f32 if f32 else lib().dgmg_prolongate_add
         self._check(fn(self._ctx, level, pc, px, nr))
@@ -257,7 +264,7 @@ class Problem:
         f32 = b.dtype == torch.float32
         pb, nr = self._vec(b, 0, b.dtype)
         out = torch.empty_like(b) if out is None else out
-        px, _ = self._vec(out, 0, b.dtype)
+        px = self._vec_like(out, 0, b.dtype, nr, "out")
         self._sync_stream()
         fn = lib().dgmg_coarse_solve_f32 if f32 else lib().dgmg_coarse_solve
         self._check(fn(self._ctx, pb, px, nr))
@@ -268,18 +275,31 @@ class Problem:
         torch = _torch()
         level = self._lvl(level)
         pa, nr = self._vec(a, level, torch.float64)
-        pb, _ = self._vec(b, level, torch.float64)
+        pb = self._vec_like(b, level, torch.float64, nr, "b")
         out = np.zeros(nr)
         self._sync_stream()
         self._check(lib().dgmg_dot(self._ctx, level, pa, pb, nr, out.ctypes.data))
         return out
+
+    def adjoint_dkappa(self, lam, u):
+        """Coefficient gradient -lambda_j^T A_1 u_j per right-hand side (numpy
+        array) and its sum over the right-hand sides (float), computed by the
+        library."""
+        torch = _torch()
+        pl, nr = self._vec(lam, self.L, torch.float64)
+        pu = self._vec_like(u, self.L, torch.float64, nr, "u")
+        per = np.zeros(nr)
+        tot = ctypes.c_double(0.0)
+        self._sync_stream()
+        self._check(lib().dgmg_adjoint_dkappa(self._ctx, pl, pu, nr, per.ctypes.data, ctypes.byref(tot)))
+        return per, tot.value
 
     def vcycle(self, b, out=None):
         torch = _torch()
         f32 = b.dtype == torch.float32
         pb, nr = self._vec(b, self.L, b.dtype)
         out = torch.empty_like(b) if out is None else out
-        px, _ = self._vec(out, self.L, b.dtype)
+        px = self._vec_like(out, self.L, b.dtype, nr, "out")
         self._sync_stream()
         fn = lib().dgmg_vcycle_f32 if f32 else lib().dgmg_vcycle
         self._check(fn(self._ctx, pb, px, nr))
@@ -289,10 +309,12 @@ class Problem:
         """PCG solve; returns (x, iters[nrhs], relres[nrhs])."""
         torch = _torch()
         pb, nr = self._vec(b, self.L, torch.float64)
-        if x0 is not None:
-            out = x0 if out is None else out.copy_(x0)
         out = torch.empty_like(b) if out is None else out
-        px, _ = self._vec(out, self.L, torch.float64)
+        px = self._vec_like(out, self.L, torch.float64, nr, "out")
+        if x0 is not None:
+            self._vec_like(x0, self.L, torch.float64, nr, "x0")
+            if x0.data_ptr() != out.data_ptr():
+                out.copy_(x0)  # the initial guess is not overwritten
         iters = np.zeros(nr, dtype=np.int32)
         relres = np.zeros(nr)
         self._sync_stream()
@@ -311,7 +333,7 @@ class Problem:
         if nr != 1:
             raise ValueError("gmres takes one right-hand side")
         out = torch.empty_like(b) if out is None else out
-        px, _ = self._vec(out, self.L, torch.float64)
+        px = self._vec_like(out, self.L, torch.float64, 1, "out")
         it = ctypes.c_int(0)
         hist = np.zeros(int(maxit) + 1)
         self._sync_stream()
@@ -337,9 +359,10 @@ def _solve_function():
     torch = _torch()
 
     class SolveFn(torch.autograd.Function):
-        """u = A(kappa)^{-1} b with A(kappa) = kappa A_1.  Backward: adjoint
-        solve with the same symmetric operator, lambda = A^{-1} g;
-        dL/db = lambda, dL/dkappa = -lambda^T A_1 u."""
+        """u = A(kappa)^{-1} b with A(kappa) = kappa A_1, b of shape (ndofs,)
+        or (nrhs, ndofs) sharing one kappa.  Backward: adjoint solve with the
+        same symmetric operator, lambda = A^{-1} g; dL/db = lambda,
+        dL/dkappa = -sum_j lambda_j^T A_1 u_j (library call)."""
 
         @staticmethod
         def forward(ctx, b, kappa, prob, rtol, maxit):
@@ -356,8 +379,8 @@ def _solve_function():
             prob = ctx.prob
             prob.set_kappa(ctx.kappa)
             lam, _, _ = prob.solve(g.contiguous(), rtol=ctx.rtol, maxit=ctx.maxit)
-            Au = prob.apply(u)  # A(kappa) u = kappa A_1 u
-            dkappa = -float(prob.dot(lam.reshape(-1), Au.reshape(-1))[0]) / ctx.kappa
+            # -sum_j lambda_j^T A_1 u_j over every right-hand side, in the library
+            _, dkappa = prob.adjoint_dkappa(lam, u)
             return lam, torch.tensor(dkappa, dtype=torch.float64, device=g.device), None, None, None
 
     return SolveFn

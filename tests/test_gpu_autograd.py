@@ -109,3 +109,68 @@ def test_full_size_poisson2d_q5_256c_adjoint():
     dk_o = closed_form_dkappa(u_o, ut, kappa)
     assert abs(gk - dk_o) <= 1e-8 * abs(dk_o)
     prob.close()
+
+
+def test_batched_right_hand_sides_share_one_kappa():
+    """b of shape (3, ndofs) with one kappa: dL/db per right-hand side equals
+    the dense adjoint, and dL/dkappa is the sum of the three single-RHS
+    gradients (dense adjoint per right-hand side); the library's per-RHS
+    values of -lambda_j^T A_1 u_j match the closed form on each."""
+    note("autograd 2-D Q2 8x8, 3 right-hand sides")
+    dim, k, L, kappa = 2, 2, 2, 0.7
+    N = 2 ** (L + 1)
+    prob = dgmg.Problem(dim, k, L, kappa=kappa, nrhs_max=3)
+    rng = np.random.default_rng(23)
+    n = prob.ndofs()
+    b = rng.standard_normal((3, n))
+    ut = 0.05 * rng.standard_normal((3, n))
+    loss, u, gb, gk = loss_and_grads(prob, b, ut, kappa, rtol=1e-13)
+    A1 = kron_operator(dim, k, N, inputs.sigma_of(k))
+    dks = []
+    for j in range(3):
+        u_o, _, lam_o, dk_o = dense_adjoint(A1, kappa, b[j], ut[j])
+        assert np.linalg.norm(u[j] - u_o) <= 1e-10 * np.linalg.norm(u_o)
+        assert np.linalg.norm(gb[j] - lam_o) <= 1e-9 * np.linalg.norm(lam_o)
+        dks.append(dk_o)
+    assert abs(gk - sum(dks)) <= 1e-9 * sum(abs(d) for d in dks)
+    # the library call itself, per right-hand side
+    lam = torch.from_numpy(gb).cuda()
+    per, tot = prob.adjoint_dkappa(lam, torch.from_numpy(u).cuda())
+    for j in range(3):
+        assert abs(per[j] - closed_form_dkappa(u[j], ut[j], kappa)) <= 1e-9 * abs(dks[j])
+    assert tot == sum(per.tolist())  # summed in index order
+    prob.close()
+
+
+def test_mismatched_right_hand_side_counts_raise():
+    """Every secondary tensor must hold as many right-hand sides as the first
+    one; the binding raises before any launch."""
+    note("binding nrhs checks")
+    prob = dgmg.Problem(2, 2, 2, nrhs_max=2)
+    n, nc = prob.ndofs(), prob.ndofs(1)
+    two = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+    one = torch.zeros(n, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        prob.apply(two, out=one)
+    with pytest.raises(ValueError):
+        prob.smooth(two, one)
+    with pytest.raises(ValueError):
+        prob.restrict_residual(two, one)
+    with pytest.raises(ValueError):
+        prob.prolongate_add(torch.zeros(nc, dtype=torch.float64, device="cuda"), two)
+    with pytest.raises(ValueError):
+        prob.vcycle(two, out=one)
+    with pytest.raises(ValueError):
+        prob.dot(two, one)
+    with pytest.raises(ValueError):
+        prob.solve(two, out=one)
+    with pytest.raises(ValueError):
+        prob.solve(two, x0=one)
+    with pytest.raises(ValueError):
+        prob.adjoint_dkappa(two, one)
+    # x0 is not overwritten by the solve
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    x0 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    x, _, _ = prob.solve(b, x0=x0)
+    assert float(x0.abs().max()) == 0.0 and float(x.abs().max()) > 0.0
+    prob.close()
