@@ -172,6 +172,21 @@ dgmg_status dgmg_coarse_solve_f32(dgmg_ctx* ctx, const float* b, float* x, int n
 dgmg_status dgmg_vcycle(dgmg_ctx* ctx, const double* b, double* x, int nrhs);
 dgmg_status dgmg_vcycle_f32(dgmg_ctx* ctx, const float* b, float* x, int nrhs);
 
+/* For callers that cannot allocate device memory during the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same V-cycle as dgmg_vcycle, same arguments, same kernels and the same
+ * result, but the vectors it needs besides b and x -- b and x on levels
+ * 0..L-1, for an FP32 V-cycle also the finest level's FP32 copies, for the
+ * Full smoother the second copies of x on levels 1..L -- live in one
+ * library-wide device array of 64 MiB per GPU (kept until the process ends)
+ * instead of the context's own vectors.  No allocation, no graph.  Returns
+ * DGMG_ERR_ARG (message from dgmg_last_error) when those vectors would not
+ * fit in 64 MiB, e.g. a 3-D Q3 32^3 FP64 cycle holds at most 14 right-hand
+ * sides.  Every call on one GPU shares that array: calls that overlap on one
+ * GPU (two streams, two contexts, two threads) race and must be ordered by
+ * the caller.  Nothing in the array needs to start at zero. */
+dgmg_status dgmg_vcycle_noalloc(dgmg_ctx* ctx, const double* b, double* x, int nrhs);
+
 /* Solve A_L x = b by CG preconditioned with one V-cycle per iteration; FP64
  * outer iteration (residual, operator, inner products); beta by the flexible
  * (Polak-Ribiere) formula when the V-cycle runs in FP32.  Stops when

@@ -32,8 +32,9 @@ def _jobs():
         for k in DEGREES:
             obj = os.path.join(OBJ, f"kernels_d{d}_k{k}.o")
             out.append([HIPCC] + COMMON + DEVICE + [f"-DDGMG_D={d}", f"-DDGMG_K={k}", "-c", src, "-o", obj])
-    out.append([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "dgmg_blas.hip"), "-o",
-                                            os.path.join(OBJ, "blas.o")])
+    for name in ("blas", "scratch"):
+        out.append([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, f"dgmg_{name}.hip"), "-o",
+                                                os.path.join(OBJ, f"{name}.o")])
     for name in ("dgmg_setup", "dgmg_api"):
         out.append([HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-c",
                                         os.path.join(CSRC, name + ".cpp"), "-o",

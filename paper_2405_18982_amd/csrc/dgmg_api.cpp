@@ -20,6 +20,7 @@
 #include "../../include/dgmg.h"
 #include "dgmg_blas.h"
 #include "dgmg_internal.h"
+#include "dgmg_scratch.h"
 #include "dgmg_setup.h"
 
 #define DGMG_API extern "C" __attribute__((visibility("default")))
@@ -159,7 +160,7 @@ struct dgmg_ctx {
     double us = 0;
   };
   Tuning tune_apply[2];
-  Tuning tune_smooth[2][21];  // per precision and level
+  Tuning tune_smooth[2][dgmg::kMaxLevels];  // per precision and level
   hipStream_t cap_stream = nullptr;
   std::vector<hipGraphExec_t> vc_graph;  // index nrhs - 1
   // the FP32 V-cycle alone (finest-level b32 -> x32), for the CG with an
@@ -171,6 +172,9 @@ struct dgmg_ctx {
   double *gm_V = nullptr, *gm_Z = nullptr, *gm_s = nullptr, *gm_partial = nullptr;
   double* gm_h = nullptr;
   int gm_cap = 0;
+  // device address of the library's scratch array on this context's device
+  // (dgmg_vcycle_noalloc), looked up in dgmg_setup_levels
+  void* scratch = nullptr;
   std::string err;
 };
 
@@ -321,17 +325,21 @@ dgmg_status ensure_alt(dgmg_ctx* c);
 // number) the result is back in x.  from_zero: the step starts from x = 0
 // (pre-smoothing in the V-cycle); colour 0 then takes r = b and writes every
 // node, so x need not be cleared first.
+// alt: the second copy of x for the Full smoother (nullptr: the level's own).
 template <typename T>
 dgmg_status op_smooth(dgmg_ctx* c, int l, T* x, const T* b, int reverse, int nrhs,
-                      bool from_zero = false) {
+                      bool from_zero = false, T* alt = nullptr) {
   const double sc = level_scale(c, l);
   const int nc = 1 << c->dim;
   const bool full = c->variant == DGMG_SMOOTH_FULL;
   T* cur = x;
   T* other = nullptr;
   if (full) {
-    RET_IF(ensure_alt<T>(c));
-    other = lvalt<T>(c->lv[l]);
+    if (!alt) {
+      RET_IF(ensure_alt<T>(c));
+      alt = lvalt<T>(c->lv[l]);
+    }
+    other = alt;
   }
   for (int i = 0; i < nc; ++i) {
     const int col = reverse ? nc - 1 - i : i;
@@ -427,43 +435,79 @@ dgmg_status ensure_levels(dgmg_ctx* c, int upto) {
     if (s_ != DGMG_OK) return s_;          \
   } while (0)
 
-// x = V(b) on level L with b, x given (may be caller or library buffers);
-// coarser levels use the library's vectors of precision T.
+// Vectors of precision T on levels 0..L-1 (b, x) and the Full smoother's
+// second copies on levels 1..L (alt), for one V-cycle.
 template <typename T>
-dgmg_status vcycle_T(dgmg_ctx* c, const T* bL, T* xL, int nrhs) {
-  RET(ensure_levels<T>(c, c->L - 1));
+struct VBufs {
+  T* b[dgmg::kMaxLevels] = {};
+  T* x[dgmg::kMaxLevels] = {};
+  T* alt[dgmg::kMaxLevels] = {};
+};
+
+// x = V(b) on level L with b, x given (may be caller or library buffers);
+// coarser levels use the vectors of `bufs`, else the library's own of
+// precision T.
+template <typename T>
+dgmg_status vcycle_T(dgmg_ctx* c, const T* bL, T* xL, int nrhs, const VBufs<T>* bufs = nullptr) {
+  if (!bufs) RET(ensure_levels<T>(c, c->L - 1));
   const int L = c->L;
-  auto B = [&](int l) -> const T* { return l == L ? bL : lvb<T>(c->lv[l]); };
-  auto X = [&](int l) -> T* { return l == L ? xL : lvx<T>(c->lv[l]); };
+  auto Bw = [&](int l) -> T* { return bufs ? bufs->b[l] : lvb<T>(c->lv[l]); };
+  auto B = [&](int l) -> const T* { return l == L ? bL : Bw(l); };
+  auto X = [&](int l) -> T* { return l == L ? xL : (bufs ? bufs->x[l] : lvx<T>(c->lv[l])); };
+  auto Alt = [&](int l) -> T* { return bufs ? bufs->alt[l] : nullptr; };
   // levels 1 and 0 (2-D: 2, 1 and 0) in one launch (same arithmetic as the
   // separate kernels)
   const bool fuse = c->fuse_bottom && kset<T>(c).bottom && c->variant != DGMG_SMOOTH_FULL;
   const bool fuse3 = fuse && c->fuse_bottom >= 2 && kset<T>(c).bottom3 && L >= 2;
   const int lo = fuse3 ? 3 : fuse ? 2 : 1;
   for (int l = L; l >= lo; --l) {
-    RET(op_smooth<T>(c, l, X(l), B(l), 0, nrhs, true));
-    RET(op_restrict<T>(c, l, X(l), B(l), lvb<T>(c->lv[l - 1]), nrhs));
+    RET(op_smooth<T>(c, l, X(l), B(l), 0, nrhs, true, Alt(l)));
+    RET(op_restrict<T>(c, l, X(l), B(l), Bw(l - 1), nrhs));
   }
   if (fuse3) {
     const double s2 = level_scale(c, 2), s1 = level_scale(c, 1);
     HIPCHK(c, kset<T>(c).bottom3(tab_of<T>(c), c->variant, (T)s2, (T)(1.0 / s2), (T)s1, (T)(1.0 / s1),
-                                 (T)(1.0 / level_scale(c, 0)), X(2), B(2), X(1), lvb<T>(c->lv[1]),
-                                 lvb<T>(c->lv[0]), X(0), nrhs, c->lv[2].ndof, c->lv[1].ndof,
-                                 c->lv[0].ndof, c->stream));
+                                 (T)(1.0 / level_scale(c, 0)), X(2), B(2), X(1), Bw(1), Bw(0), X(0),
+                                 nrhs, c->lv[2].ndof, c->lv[1].ndof, c->lv[0].ndof, c->stream));
   } else if (fuse) {
     const double s1 = level_scale(c, 1);
     const int split = (c->fuse_bottom >= 2 && kset<T>(c).bottom_split) ? 1 : 0;
     HIPCHK(c, kset<T>(c).bottom(tab_of<T>(c), c->variant, split, (T)s1, (T)(1.0 / s1),
-                                (T)(1.0 / level_scale(c, 0)), X(1), B(1), lvb<T>(c->lv[0]),
-                                X(0), nrhs, c->lv[1].ndof, c->lv[0].ndof, c->stream));
+                                (T)(1.0 / level_scale(c, 0)), X(1), B(1), Bw(0), X(0), nrhs,
+                                c->lv[1].ndof, c->lv[0].ndof, c->stream));
   } else {
     RET(op_coarse<T>(c, B(0), X(0), nrhs));
   }
   for (int l = lo; l <= L; ++l) {
     RET(op_prolong<T>(c, l, X(l - 1), X(l), nrhs));
-    RET(op_smooth<T>(c, l, X(l), B(l), 1, nrhs));
+    RET(op_smooth<T>(c, l, X(l), B(l), 1, nrhs, false, Alt(l)));
   }
   return DGMG_OK;
+}
+
+// Carve the vectors of one V-cycle of precision T for nrhs right-hand sides
+// out of the scratch array (256-byte aligned pieces): b and x on levels
+// 0..L-1, with `finest` also on level L (the FP32 V-cycle's input and output),
+// and the Full smoother's second copies on levels 1..L.  Returns the bytes
+// needed; fills `out` only if they fit in `cap`.
+template <typename T>
+size_t carve_scratch(const dgmg_ctx* c, int nrhs, bool finest, unsigned char* base, size_t cap,
+                     VBufs<T>& out) {
+  size_t used = 0;
+  auto take = [&](long long count) -> T* {
+    const size_t bytes = ((size_t)count * sizeof(T) + 255) & ~size_t(255);
+    T* p = (used + bytes <= cap) ? (T*)(base + used) : nullptr;
+    used += bytes;
+    return p;
+  };
+  const int top = finest ? c->L : c->L - 1;
+  for (int l = 0; l <= top; ++l) {
+    out.b[l] = take(c->lv[l].ndof * nrhs);
+    out.x[l] = take(c->lv[l].ndof * nrhs);
+  }
+  if (c->variant == DGMG_SMOOTH_FULL)
+    for (int l = 1; l <= c->L; ++l) out.alt[l] = take(c->lv[l].ndof * nrhs);
+  return used;
 }
 
 // z = V(r) in the context precision (FP64 vectors in and out).
@@ -633,6 +677,7 @@ DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int sm
   HIPCHK(c, hipHostMalloc((void**)&c->rec, sizeof(double) * 4 * nrhs_max));
   HIPCHK(c, hipHostGetDevicePointer((void**)&c->rec_dev, c->rec, 0));
   HIPCHK(c, hipEventCreateWithFlags(&c->ev_check, hipEventDisableTiming));
+  HIPCHK(c, dgmg::scratch_address(&c->scratch));
   c->ready = true;
   if (vcycle_precision == DGMG_FP64) RET(ensure_levels<double>(c, c->L - 1));
   else RET(ensure_levels<float>(c, c->L));
@@ -771,6 +816,41 @@ DGMG_API dgmg_status dgmg_vcycle(dgmg_ctx* c, const double* b, double* x, int nr
   RET(check_level(c, c ? c->L : 0, 0, nrhs));
   if (!x || !b) return fail(c, DGMG_ERR_ARG, "null vector");
   return precondition(c, b, x, nrhs);
+}
+
+// dgmg_vcycle with the coarse-level vectors (and, for an FP32 V-cycle, the
+// finest level's FP32 copies; for the Full smoother, the second copies of x)
+// in the library's per-device scratch array instead of the context's own
+// vectors; no graph, no allocation.  Shares the kernels of dgmg_vcycle.
+DGMG_API dgmg_status dgmg_vcycle_noalloc(dgmg_ctx* c, const double* b, double* x, int nrhs) {
+  RET(check_level(c, c ? c->L : 0, 0, nrhs));
+  if (!x || !b) return fail(c, DGMG_ERR_ARG, "null vector");
+  if (!c->scratch) return fail(c, DGMG_ERR_STATE, "scratch array address not available");
+  unsigned char* base = (unsigned char*)c->scratch;
+  char msg[160];
+  if (c->prec == 64) {
+    VBufs<double> bufs;
+    const size_t need = carve_scratch<double>(c, nrhs, false, base, dgmg::kScratchBytes, bufs);
+    if (need > dgmg::kScratchBytes) {
+      std::snprintf(msg, sizeof msg, "vcycle_noalloc needs %zu bytes of scratch, the maximum is %zu",
+                    need, dgmg::kScratchBytes);
+      return fail(c, DGMG_ERR_ARG, msg);
+    }
+    return vcycle_T<double>(c, b, x, nrhs, &bufs);
+  }
+  VBufs<float> bufs;
+  const size_t need = carve_scratch<float>(c, nrhs, true, base, dgmg::kScratchBytes, bufs);
+  if (need > dgmg::kScratchBytes) {
+    std::snprintf(msg, sizeof msg, "vcycle_noalloc needs %zu bytes of scratch, the maximum is %zu",
+                  need, dgmg::kScratchBytes);
+    return fail(c, DGMG_ERR_ARG, msg);
+  }
+  const int L = c->L;
+  const long long n = c->lv[L].ndof * nrhs;
+  HIPCHK(c, dgmg::blas_f64_to_f32(b, bufs.b[L], n, c->stream));
+  RET(vcycle_T<float>(c, bufs.b[L], bufs.x[L], nrhs, &bufs));
+  HIPCHK(c, dgmg::blas_f32_to_f64(bufs.x[L], x, n, c->stream));
+  return DGMG_OK;
 }
 
 DGMG_API dgmg_status dgmg_vcycle_f32(dgmg_ctx* c, const float* b, float* x, int nrhs) {

@@ -8,6 +8,7 @@
 namespace dgmg {
 
 constexpr int kMaxDegree = 7;
+constexpr int kMaxLevels = 21;   // levels 0..20 (finest level L <= 20)
 constexpr int kApplyShapes = 3;   // workgroup shapes of apply (2: face data in registers)
 constexpr int kSmoothShapes = 8;  // workgroup shape x prefetch of b x two waves per patch / one patch per workgroup
 

@@ -47,6 +47,7 @@ SIGNATURES = {
     "dgmg_coarse_solve_f32": (_I, [_P, _P, _P, _I]),
     "dgmg_vcycle": (_I, [_P, _P, _P, _I]),
     "dgmg_vcycle_f32": (_I, [_P, _P, _P, _I]),
+    "dgmg_vcycle_noalloc": (_I, [_P, _P, _P, _I]),
     "dgmg_pcg_solve": (_I, [_P, _P, _P, _I, _D, _I, _I, _P, _P]),
     "dgmg_gmres_solve": (_I, [_P, _P, _P, _D, _I, _P, _P]),
     "dgmg_dot": (_I, [_P, _I, _P, _P, _I, _P]),
@@ -303,6 +304,16 @@ class Problem:
         self._sync_stream()
         fn = lib().dgmg_vcycle_f32 if f32 else lib().dgmg_vcycle
         self._check(fn(self._ctx, pb, px, nr))
+        return out
+
+    def vcycle_noalloc(self, b, out):
+        """dgmg_vcycle_noalloc: the V-cycle with its level vectors in the
+        library's scratch array; b and out are FP64 and caller-allocated."""
+        torch = _torch()
+        pb, nr = self._vec(b, self.L, torch.float64)
+        px = self._vec_like(out, self.L, torch.float64, nr, "out")
+        self._sync_stream()
+        self._check(lib().dgmg_vcycle_noalloc(self._ctx, pb, px, nr))
         return out
 
     def solve(self, b, rtol=1e-10, maxit=100, x0=None, out=None, raise_on_nonconvergence=True):
