@@ -1219,17 +1219,27 @@ void write_cache(const char* path, const std::vector<CacheEntry>& es) {
 template <typename T>
 dgmg_status tune_kernel(dgmg_ctx* c, int nrhs, bool smooth, int level, T* x, T* y,
                         dgmg_ctx::Tuning& slot) {
-  int nshapes = smooth ? dgmg::kSmoothShapes : dgmg::kApplyShapes;
-  if (smooth && !(c->variant == DGMG_SMOOTH_FULL ? kset<T>(c).smooth_hi_full : kset<T>(c).smooth_split))
-    nshapes = dgmg::kSmoothShapes / 2;  // shapes 4..7 would repeat the others
-  if (!smooth && !kset<T>(c).apply_rf) nshapes = 2;  // shape 2 would repeat shape 0
+  // candidate shapes; those that would repeat another are left out
+  std::vector<int> shapes;
+  const KernelSet<T>& ks = kset<T>(c);
+  const bool rpack = nrhs > 1 && (smooth ? ks.smooth_rpack : ks.apply_rpack);
+  if (smooth) {
+    const bool hi = c->variant == DGMG_SMOOTH_FULL ? ks.smooth_hi_full : ks.smooth_split;
+    for (int v = 0; v < (hi ? 8 : 4); ++v) shapes.push_back(v);
+    if (rpack)
+      for (int v = 8; v < 12; ++v) shapes.push_back(v);
+  } else {
+    shapes = {0, 1};
+    if (ks.apply_rf) shapes.push_back(2);
+    if (rpack) shapes.push_back(3);
+  }
   const int reps = smooth ? 3 : 20;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   double best = 1e300;
   dgmg_ctx::Tuning pick = slot;
-  for (int shape = 0; shape < nshapes; ++shape)
+  for (int shape : shapes)
     for (int remap = 0; remap < 2; ++remap) {
       slot.shape = shape;
       slot.remap = remap;

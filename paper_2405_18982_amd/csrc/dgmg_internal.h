@@ -9,8 +9,13 @@ namespace dgmg {
 
 constexpr int kMaxDegree = 7;
 constexpr int kMaxLevels = 21;   // levels 0..20 (finest level L <= 20)
-constexpr int kApplyShapes = 3;   // workgroup shapes of apply (2: face data in registers)
-constexpr int kSmoothShapes = 8;  // workgroup shape x prefetch of b x two waves per patch / one patch per workgroup
+// workgroup shapes of apply: 0, 1 patches per workgroup; 2 face data in
+// registers; 3 several right-hand sides of one patch per workgroup
+constexpr int kApplyShapes = 4;
+// workgroup shapes of the smoother: 0..7 patches per workgroup x prefetch of
+// b x (two waves per patch | one patch per workgroup); 8..11 several
+// right-hand sides of one patch per workgroup (two slot counts) x prefetch
+constexpr int kSmoothShapes = 12;
 
 // Reference (h = 1, kappa = 1) data of Q_K on a two-cell patch that depends
 // on the penalty, in the arithmetic type T of the kernels that read them.
@@ -46,6 +51,7 @@ struct PatchGrid {
   int off[3];  // -1, 0 or 1
   int npatch;  // product of cnt
   int xcd_remap;  // 1: give each XCD a contiguous range of patches
+  int nrhs;    // right-hand sides of the launch (set by the launchers)
 };
 
 // Host-visible launchers of one (D, K) instantiation.  All vectors are
@@ -58,6 +64,10 @@ struct KernelSet {
                          long long ndof, hipStream_t s);
   // 1 where apply shape 2 (face data in registers) differs from shape 0
   int apply_rf;
+  // 1 where the right-hand-side-packed shapes (apply 3, smoother 8..11) hold
+  // more than one slot per workgroup
+  int apply_rpack;
+  int smooth_rpack;
   hipError_t (*mass)(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
                      long long ndof, hipStream_t s);
   // variant: DGMG_SMOOTH_* of the context.  The Dirichlet kernels update x in

@@ -432,6 +432,25 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks, int remap) {
   return xcd * q + (xcd < r ? xcd : r) + idx;
 }
 
+// Patch and right-hand side of workgroup slot `slot`: PPB patches of one
+// right-hand side per workgroup, or (RP, right-hand-side packing) one patch
+// for PPB consecutive right-hand sides, so that every slot of the workgroup
+// has the same patch type and position (uniform branches and scalar loads of
+// the 1-D data where slots share a wave); slots past the last right-hand side
+// get an out-of-range patch index and only meet the barriers.
+template <int PPB, bool RP>
+__device__ __forceinline__ void slot_work(const PatchGrid& g, int slot, int& pid, int& rhs) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap);
+  if constexpr (RP) {
+    rhs = (int)blockIdx.y * PPB + slot;
+    pid = rhs < g.nrhs ? blk : g.npatch;
+    if (rhs >= g.nrhs) rhs = 0;
+  } else {
+    pid = blk * PPB + slot;
+    rhs = blockIdx.y;
+  }
+}
+
 // Patch coordinates of patch index pid of a launch.
 struct PatchPos {
   int lo[3];
@@ -987,19 +1006,20 @@ struct Smem {
 };
 
 // ---------------------------------------------------------------- apply
-template <typename T, int PPB>
+template <typename T, int PPB, bool RP = false>
 __global__ void __launch_bounds__(TPP * PPB)
 k_apply(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
         T* __restrict__ y, long long ndof) {
   constexpr int PP = Smem<2, (D - 1) * 2 * 2 * NF>::per_patch;
   __shared__ T smem[PPB * PP];
   const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
-  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
+  int pid, rhs;
+  slot_work<PPB, RP>(g, slot, pid, rhs);
   const bool active = pid < g.npatch;
   T* A = smem + slot * PP;
   T* B = A + TS;
   T* ext = B + TS;
-  const long long roff = (long long)blockIdx.y * ndof;
+  const long long roff = (long long)rhs * ndof;
   const T* xr = x + roff;
   T* yr = y + roff;
   const PatchPos P = patch_pos(g, active ? pid : 0);
@@ -1044,20 +1064,22 @@ k_apply(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restri
 // CU instead of one).
 constexpr bool kApplyRF = (D == 3);
 
-template <typename T, int PPB>
+template <typename T, int PPB, bool RP = false>
 __global__ void __launch_bounds__(TPP * PPB)
 k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
            T* __restrict__ y, long long ndof) {
-  static_assert(kApplyRF && (!kZShfl || TPP * PPB <= 64), "cross-lane reads stay in one wave");
+  // cross-lane reads stay within a patch's lanes, which lie in one wave
+  static_assert(kApplyRF, "3-D only");
   constexpr int PP = 2 * TS + (kZShfl ? 0 : 4 * NF);
   __shared__ T smem[PPB * PP];
   const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
   const int wl = threadIdx.x & 63;
-  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
+  int pid, rhs;
+  slot_work<PPB, RP>(g, slot, pid, rhs);
   const bool active = pid < g.npatch;
   T* A = smem + slot * PP;
   T* B = A + TS;
-  const long long roff = (long long)blockIdx.y * ndof;
+  const long long roff = (long long)rhs * ndof;
   const T* xr = x + roff;
   T* yr = y + roff;
   const int N = g.N;
@@ -1452,16 +1474,17 @@ __device__ __forceinline__ void smooth_body(const Tab<K, T>* __restrict__ t, con
   }
 }
 
-template <typename T, int PPB, int MODE, bool PREFETCH, bool ZERO = false>
+template <typename T, int PPB, int MODE, bool PREFETCH, bool ZERO = false, bool RP = false>
 __global__ void __launch_bounds__(TPP * PPB)
 k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
          const T* __restrict__ xin, T* __restrict__ xout, const T* __restrict__ b, long long ndof) {
   constexpr int PP = smooth_pp<MODE>();
   __shared__ T smem[PPB * PP];
   const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
-  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
+  int pid, rhs;
+  slot_work<PPB, RP>(g, slot, pid, rhs);
   smooth_body<T, MODE, PREFETCH, ZERO>(t, g, scale, inv_scale, xin, xout, b, ndof, pid, lane,
-                                       smem + slot * PP, blockIdx.y);
+                                       smem + slot * PP, rhs);
 }
 
 
@@ -2322,10 +2345,25 @@ struct Shape {
       (V == 1 && TPP * PPB_DEFAULT * 2 > 256) ? PPB_DEFAULT : PPB_DEFAULT * (V + 1);
 };
 
+// Slots of the right-hand-side-packed shapes: at most 8 (3-D) or 16 (2-D)
+// per workgroup, within 1024 threads and half the LDS of a CU.
+template <typename T, int PP>
+constexpr int rpack_slots() {
+  int r = (D == 3) ? 8 : 16;
+  while (r > 1 && (TPP * r > 1024 || r * PP * (int)sizeof(T) > 80 * 1024)) r /= 2;
+  return r;
+}
+template <typename T>
+constexpr int rpack_apply_slots() {
+  return kApplyRF ? rpack_slots<T, 2 * TS + (kZShfl ? 0 : 4 * NF)>()
+                  : rpack_slots<T, Smem<2, (D - 1) * 2 * 2 * NF>::per_patch>();
+}
+
 template <typename T, int V>
 hipError_t launch_apply(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
                         long long ndof, hipStream_t s) {
   constexpr int PPB = Shape<V>::PPB;
+  g.nrhs = nrhs;
   dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
   hipLaunchKernelGGL((k_apply<T, PPB>), grid, dim3(TPP * PPB), 0, s,
                      (const Tab<K, T>*)tab, g, scale, x, y, ndof);
@@ -2339,11 +2377,28 @@ hipError_t launch_apply_rf(const void* tab, PatchGrid g, T scale, const T* x, T*
     return launch_apply<T, 0>(tab, g, scale, x, y, nrhs, ndof, s);
   } else {
     constexpr int PPB = PPB_DEFAULT;
+    g.nrhs = nrhs;
     dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
     hipLaunchKernelGGL((k_apply_rf<T, PPB>), grid, dim3(TPP * PPB), 0, s,
                        (const Tab<K, T>*)tab, g, scale, x, y, ndof);
     return hipGetLastError();
   }
+}
+// shape 3: one patch for several right-hand sides per workgroup (face data
+// in registers in 3-D)
+template <typename T>
+hipError_t launch_apply_rpack(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
+                              long long ndof, hipStream_t s) {
+  constexpr int R = rpack_apply_slots<T>();
+  g.nrhs = nrhs;
+  const dim3 grid(g.npatch, (nrhs + R - 1) / R), block(TPP * R);
+  if constexpr (kApplyRF)
+    hipLaunchKernelGGL((k_apply_rf<T, R, true>), grid, block, 0, s, (const Tab<K, T>*)tab, g, scale, x, y,
+                       ndof);
+  else
+    hipLaunchKernelGGL((k_apply<T, R, true>), grid, block, 0, s, (const Tab<K, T>*)tab, g, scale, x, y,
+                       ndof);
+  return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_mass(const void* tab, PatchGrid g, T scale, const T* x, T* y, int nrhs,
@@ -2361,14 +2416,61 @@ hipError_t launch_mass(const void* tab, PatchGrid g, T scale, const T* x, T* y, 
 // as bit 2 clear; variant 0 / 1 / 2 / 3: Dirichlet consistent / Dirichlet with
 // the paper's residual / Full / clamped
 constexpr bool kOnePatchShape = !kSplitOK && PPB_DEFAULT > 1;
+// shapes 8..11 (bit 3): one patch for several right-hand sides per workgroup,
+// bit 0 selecting the larger slot count, bit 1 the prefetch of b
+template <typename T>
+constexpr int rpack_smooth_slots(bool large) {
+  constexpr int r = rpack_slots<T, smooth_pp<3>()>();
+  return large ? r : (r > 1 ? r / 2 : 1);
+}
+template <typename T, int R, bool PF>
+hipError_t launch_smooth_rpack(const Tab<K, T>* tb, PatchGrid g, T scale, T inv_scale, int variant,
+                               int zero, const T* xin, T* xout, const T* b, int nrhs, long long ndof,
+                               hipStream_t s) {
+  const dim3 grid(g.npatch, (nrhs + R - 1) / R), block(TPP * R);
+  if (zero) {
+    if (variant == 2)
+      hipLaunchKernelGGL((k_smooth<T, R, 3, false, true, true>), grid, block, 0, s, tb, g, scale,
+                         inv_scale, xin, xout, b, ndof);
+    else if (variant == 3)
+      hipLaunchKernelGGL((k_smooth<T, R, 4, false, true, true>), grid, block, 0, s, tb, g, scale,
+                         inv_scale, xout, xout, b, ndof);
+    else if (variant == 1)
+      hipLaunchKernelGGL((k_smooth<T, R, 2, false, true, true>), grid, block, 0, s, tb, g, scale,
+                         inv_scale, xout, xout, b, ndof);
+    else
+      hipLaunchKernelGGL((k_smooth<T, R, 1, false, true, true>), grid, block, 0, s, tb, g, scale,
+                         inv_scale, xout, xout, b, ndof);
+    return hipGetLastError();
+  }
+  if (variant == 2)
+    hipLaunchKernelGGL((k_smooth<T, R, 3, PF, false, true>), grid, block, 0, s, tb, g, scale, inv_scale,
+                       xin, xout, b, ndof);
+  else if (variant == 3)
+    hipLaunchKernelGGL((k_smooth<T, R, 4, PF, false, true>), grid, block, 0, s, tb, g, scale, inv_scale,
+                       xout, xout, b, ndof);
+  else if (variant == 1)
+    hipLaunchKernelGGL((k_smooth<T, R, 2, PF, false, true>), grid, block, 0, s, tb, g, scale, inv_scale,
+                       xout, xout, b, ndof);
+  else
+    hipLaunchKernelGGL((k_smooth<T, R, 1, PF, false, true>), grid, block, 0, s, tb, g, scale, inv_scale,
+                       xout, xout, b, ndof);
+  return hipGetLastError();
+}
 template <typename T, int V>
 hipError_t launch_smooth(const void* tab, PatchGrid g, T scale, T inv_scale, int variant, int zero,
                          const T* xin, T* xout, const T* b, int nrhs, long long ndof, hipStream_t s) {
   constexpr int PPB = (kOnePatchShape && (V & 4)) ? 1 : Shape<(V & 1)>::PPB;
   constexpr bool PF = (V & 2) != 0;
   constexpr bool SPLIT = (V & 4) != 0 && kSplitOK;
-  dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
+  g.nrhs = nrhs;
   const Tab<K, T>* tb = (const Tab<K, T>*)tab;
+  if constexpr ((V & 8) != 0) {
+    constexpr int R = rpack_smooth_slots<T>((V & 1) != 0);
+    return launch_smooth_rpack<T, R, PF>(tb, g, scale, inv_scale, variant, zero, xin, xout, b, nrhs, ndof,
+                                         s);
+  }
+  dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
   if constexpr (SPLIT) {
     if (variant != 2) {
       const dim3 block(2 * TPP * PPB);
@@ -2513,7 +2615,10 @@ KernelSet<T> make_set() {
   k.apply[0] = &launch_apply<T, 0>;
   k.apply[1] = &launch_apply<T, 1>;
   k.apply[2] = &launch_apply_rf<T>;
+  k.apply[3] = &launch_apply_rpack<T>;
   k.apply_rf = kApplyRF ? 1 : 0;
+  k.apply_rpack = rpack_apply_slots<T>() > 1 ? 1 : 0;
+  k.smooth_rpack = rpack_smooth_slots<T>(true) > 1 ? 1 : 0;
   k.mass = &launch_mass<T>;
   k.smooth[0] = &launch_smooth<T, 0>;
   k.smooth[1] = &launch_smooth<T, 1>;
@@ -2523,6 +2628,10 @@ KernelSet<T> make_set() {
   k.smooth[5] = &launch_smooth<T, 5>;
   k.smooth[6] = &launch_smooth<T, 6>;
   k.smooth[7] = &launch_smooth<T, 7>;
+  k.smooth[8] = &launch_smooth<T, 8>;
+  k.smooth[9] = &launch_smooth<T, 9>;
+  k.smooth[10] = &launch_smooth<T, 10>;
+  k.smooth[11] = &launch_smooth<T, 11>;
   k.smooth_split = (kSplitOK || kOnePatchShape) ? 1 : 0;
   k.smooth_hi_full = kOnePatchShape ? 1 : 0;
   k.restrict_residual = &launch_restrict<T>;

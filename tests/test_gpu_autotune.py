@@ -31,10 +31,10 @@ def rel(a, b):
 
 
 def force_cache(path, dim, k, L, nrhs, shape, remap):
-    """Cache entries forcing the FP64 apply (shape mod 3) and the FP64
-    smoother on every level (shape 0..7) to one choice."""
+    """Cache entries forcing the FP64 apply (shape mod 4) and the FP64
+    smoother on every level (shape 0..11) to one choice."""
     lines = []
-    keys = [("apply", shape % 3)] + [(f"smooth/l{l}", shape) for l in range(1, L + 1)]
+    keys = [("apply", shape % 4)] + [(f"smooth/l{l}", shape) for l in range(1, L + 1)]
     for kern, sh in keys:
         key = f"gfx950/d{dim}/k{k}/L{L}/nrhs{nrhs}/fp64/{kern}"
         lines.append(f'  "{key}": {{"shape": {sh}, "remap": {remap}, "us": 1.000}}')
@@ -42,7 +42,7 @@ def force_cache(path, dim, k, L, nrhs, shape, remap):
 
 
 @pytest.mark.parametrize("dim,k,L", [(2, 2, 3), (2, 5, 2), (3, 1, 2), (3, 2, 2), (3, 3, 2), (3, 4, 1)])
-@pytest.mark.parametrize("shape,remap", list(itertools.product(range(8), [0, 1])))
+@pytest.mark.parametrize("shape,remap", list(itertools.product(range(12), [0, 1])))
 def test_every_tunable_shape_matches_oracle(tmp_path, dim, k, L, shape, remap):
     note(f"tuned shape={shape} remap={remap} d={dim} k={k} L={L}")
     nrhs = 2
@@ -143,3 +143,47 @@ def test_register_face_apply_is_bitwise_lds_apply(tmp_path, dim, k, L):
     A = kron_operator(dim, k, 2 ** (L + 1), inputs.sigma_of(k))
     for j in range(nrhs):
         assert rel(outs[2][j].numpy(), A @ X[j]) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,k,L", [(2, 2, 3), (2, 5, 2), (3, 1, 2), (3, 3, 2), (3, 4, 1), (3, 7, 1)])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("precision", [64, 32])
+def test_rhs_packed_shapes_are_bitwise_patch_packed(tmp_path, dim, k, L, variant, precision):
+    """Shapes that hold one patch for several right-hand sides per workgroup
+    (apply 3, smoother 8..11) compute every output with the operations of
+    the patch-packed shapes (apply 0, smoother 0..3): equal bit for bit for a
+    smoothing step, a V-cycle and the apply, with a right-hand-side count (5)
+    that leaves the last workgroup partly empty."""
+    if variant == 3 and k < 3:
+        pytest.skip("the clamped kernel needs k >= 3")
+    note(f"rhs-packed bitwise d={dim} k={k} L={L} variant={variant} fp{precision}")
+    nrhs = 5
+    dt = torch.float64 if precision == 64 else torch.float32
+    X = inputs.uniform(81, (nrhs, 2 ** ((L + 1) * dim) * (k + 1) ** dim))
+    B = inputs.uniform(82, X.shape)
+    outs = {}
+    for sm, ap in ((0, 0), (8, 3), (2, 0), (11, 3)):
+        prob = dgmg.Problem(dim, k, L, precision=precision, variant=variant, nrhs_max=nrhs)
+        cache = tmp_path / f"tune{sm}.json"
+        lines = [f'  "gfx950/d{dim}/k{k}/L{L}/nrhs{nrhs}/fp64/apply": {{"shape": {ap}, "remap": 1, "us": 1.000}}']
+        for l in range(1, L + 1):
+            key = f"gfx950/d{dim}/k{k}/L{L}/nrhs{nrhs}/fp{precision}/smooth/l{l}"
+            lines.append(f'  "{key}": {{"shape": {sm}, "remap": 1, "us": 1.000}}')
+        cache.write_text("{\n" + ",\n".join(lines) + "\n}\n")
+        prob.autotune(nrhs=nrhs, cache=str(cache))
+        Xg = torch.from_numpy(X).to("cuda", dt)
+        prob.smooth(Xg, torch.from_numpy(B).to("cuda", dt))
+        V = prob.vcycle(torch.from_numpy(B).to("cuda", dt))
+        Y = prob.apply(torch.from_numpy(X).to("cuda", torch.float64))
+        torch.cuda.synchronize()
+        outs[sm] = (Xg.cpu(), V.cpu(), Y.cpu())
+        prob.close()
+    for a, b in ((0, 8), (2, 11)):
+        for i in range(3):
+            assert torch.equal(outs[a][i], outs[b][i]), f"shapes {a}/{b} output {i}"
+    if precision == 64 and variant == 0:
+        A = kron_operator(dim, k, 2 ** (L + 1), inputs.sigma_of(k))
+        fs = FDSmoother(dim, k, 2 ** (L + 1), inputs.sigma_of(k))
+        for j in range(nrhs):
+            assert rel(outs[8][2][j].numpy(), A @ X[j]) <= 1e-12
+            assert rel(outs[8][0][j].numpy(), fs.step(X[j], B[j], list(range(2 ** dim)))) <= 1e-12
