@@ -402,6 +402,7 @@ def cpu_full():
     for name in ("poisson2d_q2_8x8", WORKLOAD, "poisson2d_q5_256c_adjoint"):
         H, b, w = _oracle_problem(name)
         for thr in (None, 1):
+            print(f"# {name} oracle PCG solves, threads={thr}", flush=True)
             with threadpool_limits(limits=thr):
                 t, it, rel = _oracle_solve_seconds(H, b, reps=5, warm=1)
                 emit({"workload": name, "what": "pcg solve to 1e-10", "threads": thr or _pool_threads(),
@@ -413,6 +414,7 @@ def cpu_full():
     for thr in (None, 1):
         with threadpool_limits(limits=thr):
             for nr in (1, 16):
+                print(f"# 3-D Q4 32^3 oracle apply and smoothing step, nrhs={nr}, threads={thr}", flush=True)
                 ta = _median_time(lambda: [H.apply[L](X[j]) for j in range(nr)], reps=5 if nr == 1 else 3)
                 ts = _median_time(lambda: [H.smooth(L, X[j], B[j], H.asc) for j in range(nr)],
                                   reps=5 if nr == 1 else 3)
@@ -433,8 +435,9 @@ def cpu_full():
     b = inputs.uniform(3, n)
     for thr in (None, 1):
         with threadpool_limits(limits=thr):
+            print(f"# 3-D Q7 64^3 oracle apply and colour-0 sweep, threads={thr}", flush=True)
             ta = _median_time(lambda: ap(x), reps=3)
-            tc = _median_time(lambda: sm.step(x, b, [0]), reps=1)
+            tc = _median_time(lambda: sm.step(x, b, [0]), reps=1, warm=0)
             emit({"workload": "poisson3d_q7_64c_mixed", "threads": thr or _pool_threads(), "apply_s": ta,
                   "smooth_colour0_s": tc, "smooth_step_est_s": tc * 2 ** d,
                   "note": "smoothing step estimated as 8 x the colour-0 sweep (colours have "
