@@ -79,11 +79,33 @@ struct Level {
 };
 
 template <int K, typename T>
-void fill_tab(const dgmg::HostTables& H, std::vector<unsigned char>& out) {
+void fill_tab(int dim, const dgmg::HostTables& H, std::vector<unsigned char>& out) {
   using Tb = dgmg::Tab<K, T>;
   out.assign(sizeof(Tb), 0);
   Tb* t = reinterpret_cast<Tb*>(out.data());
   constexpr int E = 2 * (K + 1);
+  // inverse eigenvalue sums, summed in the kernels' former order, in FP64
+  const std::vector<double>* lams[3] = {H.lam, H.lamf, H.lamc};
+  auto inv = [](double s) { return std::isinf(s) ? 0.0 : 1.0 / s; };
+  for (int sp = 0; sp < 3; ++sp)
+    for (int tx = 0; tx < 4; ++tx)
+      for (int ty = 0; ty < 4; ++ty) {
+        const std::vector<double>& lx = lams[sp][tx];
+        const std::vector<double>& ly = lams[sp][ty];
+        if (dim == 2) {
+          T* r = t->rs[sp][tx * 4 + ty];
+          for (int qy = 0; qy < E; ++qy)
+            for (int qx = 0; qx < E; ++qx) r[qy * E + qx] = (T)inv(lx[qx] + ly[qy]);
+          continue;
+        }
+        for (int tz = 0; tz < 4; ++tz) {
+          const std::vector<double>& lz = lams[sp][tz];
+          T* r = t->rs[sp][(tx * 4 + ty) * 4 + tz];
+          for (int qz = 0; qz < E; ++qz)
+            for (int qx = 0; qx < E; ++qx)
+              for (int qy = 0; qy < E; ++qy) r[(qz * E + qx) * E + qy] = (T)inv(ly[qy] + (lx[qx] + lz[qz]));
+        }
+      }
   t->sigma = (T)H.sigma;
   for (int ty = 0; ty < 4; ++ty) {
     for (int i = 0; i < E * E; ++i) t->S[ty][i] = (T)H.S[ty][i];
@@ -100,15 +122,15 @@ void fill_tab(const dgmg::HostTables& H, std::vector<unsigned char>& out) {
 }
 
 template <typename T>
-void fill_tab_k(int k, const dgmg::HostTables& H, std::vector<unsigned char>& out) {
+void fill_tab_k(int dim, int k, const dgmg::HostTables& H, std::vector<unsigned char>& out) {
   switch (k) {
-    case 1: fill_tab<1, T>(H, out); break;
-    case 2: fill_tab<2, T>(H, out); break;
-    case 3: fill_tab<3, T>(H, out); break;
-    case 4: fill_tab<4, T>(H, out); break;
-    case 5: fill_tab<5, T>(H, out); break;
-    case 6: fill_tab<6, T>(H, out); break;
-    default: fill_tab<7, T>(H, out); break;
+    case 1: fill_tab<1, T>(dim, H, out); break;
+    case 2: fill_tab<2, T>(dim, H, out); break;
+    case 3: fill_tab<3, T>(dim, H, out); break;
+    case 4: fill_tab<4, T>(dim, H, out); break;
+    case 5: fill_tab<5, T>(dim, H, out); break;
+    case 6: fill_tab<6, T>(dim, H, out); break;
+    default: fill_tab<7, T>(dim, H, out); break;
   }
 }
 
@@ -652,8 +674,8 @@ DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int sm
   c->tune_apply[0].shape = kset<double>(c).apply_rf ? 2 : 0;
   c->tune_apply[1].shape = kset<float>(c).apply_rf ? 2 : 0;
   std::vector<unsigned char> t64, t32;
-  fill_tab_k<double>(c->k, c->host, t64);
-  fill_tab_k<float>(c->k, c->host, t32);
+  fill_tab_k<double>(c->dim, c->k, c->host, t64);
+  fill_tab_k<float>(c->dim, c->k, c->host, t32);
   HIPCHK(c, hipMalloc(&c->tab64, t64.size()));
   HIPCHK(c, hipMalloc(&c->tab32, t32.size()));
   HIPCHK(c, hipMemcpy(c->tab64, t64.data(), t64.size(), hipMemcpyHostToDevice));

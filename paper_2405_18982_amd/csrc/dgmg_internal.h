@@ -28,6 +28,13 @@ constexpr int kSmoothShapes = 12;
 //         huge finite value)
 //   Sf[t], lamf[t] : the same on the whole patch (Full kernel)
 //   Sc[t], lamc[t] : C S on the clamped space with basis C (clamped kernel)
+//   rs[s][c] : the inverse eigenvalue sums of the fast-diagonalisation solve
+//         of local space s (0 Dirichlet, 1 whole patch, 2 clamped) for the
+//         patch-type combination c, computed in FP64 and rounded: in 3-D,
+//         c = (tx 4 + ty) 4 + tz and rs[s][c][(qz E + qx) E + qy] =
+//         1 / (lam_y[qy] + (lam_x[qx] + lam_z[qz])); in 2-D, c = tx 4 + ty and
+//         rs[s][c][qy E + qx] = 1 / (lam_x[qx] + lam_y[qy]); 0 where a slot is
+//         unused
 template <int K, typename T>
 struct Tab {
   static constexpr int n = K + 1;
@@ -39,6 +46,7 @@ struct Tab {
   T lamf[4][E];
   T Sc[4][E * E];
   T lamc[4][E];
+  T rs[3][64][E * E * E];
 };
 
 // The patches of one launch: patch m = (m_0, .., m_{D-1}), m_i < cnt[i], has

@@ -313,6 +313,18 @@ template <typename T, int SP>
 __device__ __forceinline__ const T* fd_lam(const Tab<K, T>* __restrict__ t, int ty) {
   return SP == SP_FULL ? t->lamf[ty] : SP == SP_CLAMPED ? t->lamc[ty] : t->lam[ty];
 }
+// Inverse eigenvalue sums of the scaling line of a lane (3-D: the y-line
+// (qx, qz) = (l % E, l / E); 2-D: the x-line qy = l): E values from the
+// patch-type combination's table, read at the start of a colour step so that
+// the loads overlap the operator passes.
+template <typename T, int SP>
+__device__ __forceinline__ void load_rs(const Tab<K, T>* __restrict__ t, const int (&ty)[3], int l,
+                                        T (&r)[E]) {
+  const int combo = (D == 3) ? (ty[0] * 4 + ty[1]) * 4 + ty[2] : ty[0] * 4 + ty[1];
+  const T* p = t->rs[SP == SP_FULL ? 1 : SP == SP_CLAMPED ? 2 : 0][combo] + l * E;
+#pragma unroll
+  for (int q = 0; q < E; ++q) r[q] = p[q];
+}
 
 // Interior patches (type 0) on the Dirichlet space: the 1-D problem is
 // symmetric under the reflection p -> E-1-p, and the host computes its
@@ -430,6 +442,15 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks, int remap) {
   const int q = nblocks / 8, r = nblocks % 8;
   const int xcd = b % 8, idx = b / 8;
   return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
+// Workgroup slot of the calling thread (TPP threads per slot): a scalar
+// where a slot spans whole waves, so that the patch index and position that
+// follow from it stay in scalar registers.
+__device__ __forceinline__ int slot_of() {
+  const int s = (int)threadIdx.x / TPP;
+  if constexpr (TPP % 64 == 0) return __builtin_amdgcn_readfirstlane(s);
+  return s;
 }
 
 // Patch and right-hand side of workgroup slot `slot`: PPB patches of one
@@ -583,22 +604,47 @@ __device__ __forceinline__ void gather_ext(const Tab<K, T>* __restrict__ t, cons
   }
 }
 
+// row[nu] = M[mu][nu] for a lane-dependent mu, read from a device copy of
+// the mass matrix (n vector loads instead of a select chain per entry)
+template <typename T>
+struct MassRows {
+  T v[n * n];
+};
+template <typename T>
+constexpr MassRows<T> make_mass_rows() {
+  MassRows<T> r{};
+  for (int i = 0; i < n * n; ++i) r.v[i] = T(kRef.M[i]);
+  return r;
+}
+template <typename T>
+__device__ constexpr MassRows<T> kMassRows = make_mass_rows<T>();
+
+template <typename T>
+__device__ __forceinline__ void mass_row(int mu, T (&row)[n]) {
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) row[nu] = kMassRows<T>.v[mu * n + nu];
+}
+
 // mass-contract ext entries along the first tangential coordinate for the
 // value at (a, b): sum over the cell block of a
 template <typename T>
 __device__ __forceinline__ T ext_mx(const Tab<K, T>* __restrict__ t, const T* arr, int a, int b) {
   const int c0 = (a / n) * n, mu = a % n;
+  T row[n];
+  mass_row<T>(mu, row);
   T s = T(0);
 #pragma unroll
-  for (int nu = 0; nu < n; ++nu) s += T(kRef.M[mu * n + nu]) * arr[c0 + nu + E * b];
+  for (int nu = 0; nu < n; ++nu) s += row[nu] * arr[c0 + nu + E * b];
   return s;
 }
 template <typename T>
 __device__ __forceinline__ T ext_my(const Tab<K, T>* __restrict__ t, const T* arr, int a, int b) {
   const int c0 = (b / n) * n, mu = b % n;
+  T row[n];
+  mass_row<T>(mu, row);
   T s = T(0);
 #pragma unroll
-  for (int nu = 0; nu < n; ++nu) s += T(kRef.M[mu * n + nu]) * arr[a + E * (c0 + nu)];
+  for (int nu = 0; nu < n; ++nu) s += row[nu] * arr[a + E * (c0 + nu)];
   return s;
 }
 
@@ -640,18 +686,20 @@ __device__ __forceinline__ Sides<T> yline_sides_global(const Tab<K, T>* __restri
   const int cz = (D == 3) ? P.lo[2] + pz / n : 0;
   const int az = (D == 3) ? pz % n : 0;
   const T half = T(0.5);
+  T row[n];
+  if (!sd.bl || !sd.br) mass_row<T>(mu, row);
   if (!sd.bl) {
     const T* r = x + cell_index(N, cx, P.lo[1] - 1, cz) * NC + K * n + az * n * n;
     T s = T(0);
 #pragma unroll
-    for (int nu = 0; nu < n; ++nu) s += T(kRef.M[mu * n + nu]) * r[nu];
+    for (int nu = 0; nu < n; ++nu) s += row[nu] * r[nu];
     sd.bL = -half * s;
   }
   if (!sd.br) {
     const T* r = x + cell_index(N, cx, P.lo[1] + 2, cz) * NC + az * n * n;
     T s = T(0);
 #pragma unroll
-    for (int nu = 0; nu < n; ++nu) s += T(kRef.M[mu * n + nu]) * r[nu];
+    for (int nu = 0; nu < n; ++nu) s += row[nu] * r[nu];
     sd.bR = half * s;
   }
   return sd;
@@ -715,27 +763,6 @@ __device__ __forceinline__ void read_xline(const T* __restrict__ x, long long ro
 // Lines of a patch within one wave (3-D Q1, Q3: TPP = 16 or 64 lanes): values
 // held one per lane can be contracted across lanes.
 constexpr bool kZShfl = (TPP <= 64) && (64 % TPP == 0);
-
-// row[nu] = M[mu][nu] for a lane-dependent mu, read from a device copy of
-// the mass matrix (n vector loads instead of a select chain per entry)
-template <typename T>
-struct MassRows {
-  T v[n * n];
-};
-template <typename T>
-constexpr MassRows<T> make_mass_rows() {
-  MassRows<T> r{};
-  for (int i = 0; i < n * n; ++i) r.v[i] = T(kRef.M[i]);
-  return r;
-}
-template <typename T>
-__device__ constexpr MassRows<T> kMassRows = make_mass_rows<T>();
-
-template <typename T>
-__device__ __forceinline__ void mass_row(int mu, T (&row)[n]) {
-#pragma unroll
-  for (int nu = 0; nu < n; ++nu) row[nu] = kMassRows<T>.v[mu * n + nu];
-}
 
 // sum_nu row[nu] v(lane + E (nu - mu)): the y-contraction of z-face values
 // held one per lane (wl: the lane's index in its wave)
@@ -1012,7 +1039,7 @@ k_apply(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restri
         T* __restrict__ y, long long ndof) {
   constexpr int PP = Smem<2, (D - 1) * 2 * 2 * NF>::per_patch;
   __shared__ T smem[PPB * PP];
-  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  const int slot = slot_of(), lane = threadIdx.x % TPP;
   int pid, rhs;
   slot_work<PPB, RP>(g, slot, pid, rhs);
   const bool active = pid < g.npatch;
@@ -1072,7 +1099,7 @@ k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
   static_assert(kApplyRF, "3-D only");
   constexpr int PP = 2 * TS + (kZShfl ? 0 : 4 * NF);
   __shared__ T smem[PPB * PP];
-  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  const int slot = slot_of(), lane = threadIdx.x % TPP;
   const int wl = threadIdx.x & 63;
   int pid, rhs;
   slot_work<PPB, RP>(g, slot, pid, rhs);
@@ -1215,7 +1242,7 @@ __global__ void __launch_bounds__(TPP * PPB)
 k_mass(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
        T* __restrict__ y, long long ndof) {
   __shared__ T smem[PPB * TS];
-  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  const int slot = slot_of(), lane = threadIdx.x % TPP;
   const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
   const bool active = pid < g.npatch;
   T* tile = smem + slot * TS;
@@ -1331,6 +1358,8 @@ __device__ __forceinline__ void smooth_body(const Tab<K, T>* __restrict__ t, con
     }
   }
   const int tyx = P.ty[0], tyy = P.ty[1], tyz = P.ty[2];
+  T rsl[E];  // inverse eigenvalue sums of the lane's scaling line
+  if (active) load_rs<T, SP>(t, P.ty, lane, rsl);
   Line<T> xl;  // the thread's x-line of x, kept for the final update
   // y-face couplings of the thread's y-line, read early from global (Dirichlet
   // kernels), and (PREFETCH) its line of b for the last operator pass: one
@@ -1380,19 +1409,16 @@ __device__ __forceinline__ void smooth_body(const Tab<K, T>* __restrict__ t, con
         store_line(A, base, stride, o);
       }
     __syncthreads();
-    // Y1: S_y^T, scale by 1/(sum lambda), S_y
+    // Y1: S_y^T, scale by 1/(sum lambda), S_y (one line per lane: TPP = NL)
     if (active)
       for (int i = lane; i < NL; i += TPP) {
-        const int qx = i % E, qz = i / E;
         int base, stride;
         line_geom(1, i, base, stride);
-        const T* ly = fd_lam<T, SP>(t, tyy);
-        const T lt = fd_lam<T, SP>(t, tyx)[qx] + fd_lam<T, SP>(t, tyz)[qz];
         Line<T> v, o;
         load_line(A, base, stride, v);
         line_St<T, SP>(t, tyy, v, o);
 #pragma unroll
-        for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(ly[q] + lt));
+        for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * rsl[q]);
         line_S<T, SP>(t, tyy, o, v);
         store_line(A, base, stride, v);
       }
@@ -1409,19 +1435,16 @@ __device__ __forceinline__ void smooth_body(const Tab<K, T>* __restrict__ t, con
       }
     __syncthreads();
   } else {
-    // X1: S_x^T, scale, S_x
+    // X1: S_x^T, scale, S_x (one line per lane: TPP = NL)
     if (active)
       for (int i = lane; i < NL; i += TPP) {
-        const int qy = i;
         int base, stride;
         line_geom(0, i, base, stride);
-        const T* lx = fd_lam<T, SP>(t, tyx);
-        const T lt = fd_lam<T, SP>(t, tyy)[qy];
         Line<T> v, o;
         load_line(A, base, stride, v);
         line_St<T, SP>(t, tyx, v, o);
 #pragma unroll
-        for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * recip(lx[q] + lt));
+        for (int q = 0; q < E; ++q) o.v[q] = o.v[q] * (inv_scale * rsl[q]);
         line_S<T, SP>(t, tyx, o, v);
         store_line(A, base, stride, v);
       }
@@ -1480,7 +1503,7 @@ k_smooth(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, T inv_scale,
          const T* __restrict__ xin, T* __restrict__ xout, const T* __restrict__ b, long long ndof) {
   constexpr int PP = smooth_pp<MODE>();
   __shared__ T smem[PPB * PP];
-  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  const int slot = slot_of(), lane = threadIdx.x % TPP;
   int pid, rhs;
   slot_work<PPB, RP>(g, slot, pid, rhs);
   smooth_body<T, MODE, PREFETCH, ZERO>(t, g, scale, inv_scale, xin, xout, b, ndof, pid, lane,
@@ -1717,6 +1740,13 @@ __device__ __forceinline__ void smooth_split_body(const Tab<K, T>* __restrict__ 
   const bool endz = (tyz & (H == 0 ? 1 : 2)) != 0;
   Half<T> xh;  // this half of the thread's x-line of x
   Half<T> bh;  // this half of the thread's z-line of b
+  T rsh[n];    // inverse eigenvalue sums of this half of the lane's scaling line
+  if (active) {
+    T rsl[E];
+    load_rs<T, SP>(t, P.ty, lane, rsl);
+#pragma unroll
+    for (int j = 0; j < n; ++j) rsh[j] = rsl[H * n + j];
+  }
   if (PREFETCH && active) read_lasthalf<T>(br, g.N, P, lane, H, bh);
   if constexpr (ZERO) {
 #pragma unroll
@@ -1837,17 +1867,14 @@ __device__ __forceinline__ void smooth_split_body(const Tab<K, T>* __restrict__ 
   __syncthreads();
   // Y1a: S_y^T and 1/(sum lambda), A -> B
   if (active) {
-    const int qx = lane % E, qz = lane / E;
     int base, stride;
     line_geom(1, lane, base, stride);
-    const T* ly = fd_lam<T, SP>(t, tyy);
-    const T lt = fd_lam<T, SP>(t, tyx)[qx] + fd_lam<T, SP>(t, tyz)[qz];
     Line<T> v;
     load_line(A, base, stride, v);
     Half<T> o;
     half_St<T, SP, H>(t, tyy, v, o);
 #pragma unroll
-    for (int j = 0; j < n; ++j) o.v[j] = o.v[j] * (inv_scale * recip(ly[H * n + j] + lt));
+    for (int j = 0; j < n; ++j) o.v[j] = o.v[j] * (inv_scale * rsh[j]);
     store_half(B, base, stride, H, o);
   }
   __syncthreads();
@@ -1994,7 +2021,7 @@ __global__ void __launch_bounds__(TPP * PPB)
 k_restrict(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
            const T* __restrict__ b, T* __restrict__ bc, long long ndof, long long ndof_c) {
   __shared__ T smem[PPB * kRestrictPP];
-  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  const int slot = slot_of(), lane = threadIdx.x % TPP;
   const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
   restrict_body<T>(t, g, scale, x, b, bc, ndof, ndof_c, pid, lane, smem + slot * kRestrictPP, blockIdx.y);
 }
@@ -2071,7 +2098,7 @@ __global__ void __launch_bounds__(TPP * PPB)
 k_prolong(const Tab<K, T>* __restrict__ t, PatchGrid g, const T* __restrict__ xc,
           T* __restrict__ x, long long ndof, long long ndof_c) {
   __shared__ T smem[PPB * TS];
-  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  const int slot = slot_of(), lane = threadIdx.x % TPP;
   const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
   (void)t;
   prolong_body<T>(g, xc, x, ndof, ndof_c, pid, lane, smem + slot * TS, blockIdx.y);
@@ -2233,7 +2260,7 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(TPP * kBottomSlots)
 k_bottom(const Tab<K, T>* __restrict__ t, BottomArgs<T> a) {
   __shared__ T smem[kBottomSlots * kBottomPP];
-  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  const int slot = slot_of(), lane = threadIdx.x % TPP;
   bottom_body<T, MODE>(t, a, slot, lane, smem + slot * kBottomPP, blockIdx.y);
 }
 
@@ -2262,7 +2289,7 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(TPP * kBottom3Slots)
 k_bottom3(const Tab<K, T>* __restrict__ t, Bottom3Args<T> a3) {
   __shared__ T smem[kBottom3Slots * kBottomPP];
-  const int slot = threadIdx.x / TPP, lane = threadIdx.x % TPP;
+  const int slot = slot_of(), lane = threadIdx.x % TPP;
   T* sm = smem + slot * kBottomPP;
   const int rhs = blockIdx.y;
   constexpr int NCOL = 1 << D;
