@@ -529,6 +529,15 @@ def main():
         "final_relres": float(rel[0]),
         "fp64_ms_per_solve": ms,
     }
+    # one V-cycle with the bottom levels as the dense operator (the solve's
+    # setting) and as the fused bottom launch
+    xv = torch.empty_like(b)
+    t_vc = _events_time(lambda: prob.vcycle(b, out=xv), 30)
+    prob.use_dense_bottom(False)
+    t_vc_launch = _events_time(lambda: prob.vcycle(b, out=xv), 30)
+    prob.use_dense_bottom(True)
+    c2["vcycle_us"] = {"dense_bottom": round(t_vc * 1e6, 2), "bottom_launch": round(t_vc_launch * 1e6, 2),
+                       "dense_bottom_level": prob.dense_bottom_level()}
     c2.update({k2: v for k2, v in kernel_rooflines(prob, 1, precisions=(32,)).items()})
     components = {WORKLOAD: c2}
     host_sols = {WORKLOAD: {"b": b.cpu().numpy(), "gpu_fp64": x.cpu().numpy()}}

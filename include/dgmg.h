@@ -114,6 +114,25 @@ dgmg_status dgmg_set_kappa(dgmg_ctx* ctx, double kappa);
  * host.  Both give bitwise identical results.  A new kappa drops the graphs. */
 dgmg_status dgmg_use_graphs(dgmg_ctx* ctx, int enable);
 
+/* The V-cycle's bottom as a dense operator.  The coarsest levels of the
+ * V-cycle (Sec. 3: pre-smoothing on level m, restriction, the exact solve on
+ * level 0 and, in 2-D, also on level 1, prolongation, post-smoothing on level
+ * m, with m = 1 in 3-D and m = 2 in 2-D) map the level-m right-hand side
+ * linearly to the level-m correction.  Where those levels run as one fused
+ * launch (not for the Full smoother), level m lies below the finest level and
+ * has at most 4096 DoFs, dgmg_setup_levels applies that launch to the level's
+ * unit vectors and keeps the resulting nd x nd matrix (context precision; 134
+ * MB for nd = 4096 in FP64) together with 8 x 16 x nd partial sums; a
+ * V-cycle for at most 16 right-hand sides then applies it as one
+ * matrix-vector product (the matrix read once per 8 right-hand sides), scaled
+ * by kappa_setup / kappa; more right-hand sides keep the launch, which runs
+ * them side by side.  Same linear map as the launch, other rounding order.  If the matrix cannot be allocated the launch stays in
+ * use.  enable = 0 switches back to the launch, 1 (default) to the matrix;
+ * drops the captured graphs.  dgmg_dense_bottom_level returns m, or -1 when
+ * no matrix was built. */
+dgmg_status dgmg_use_dense_bottom(dgmg_ctx* ctx, int enable);
+int dgmg_dense_bottom_level(const dgmg_ctx* ctx);
+
 /* Sizes: cells per direction and DoFs per right-hand side of a level. */
 long long dgmg_level_ndofs(const dgmg_ctx* ctx, int level);
 int dgmg_level_cells(const dgmg_ctx* ctx, int level);
@@ -184,7 +203,9 @@ dgmg_status dgmg_vcycle_f32(dgmg_ctx* ctx, const float* b, float* x, int nrhs);
  * fit in 64 MiB, e.g. a 3-D Q3 32^3 FP64 cycle holds at most 14 right-hand
  * sides.  Every call on one GPU shares that array: calls that overlap on one
  * GPU (two streams, two contexts, two threads) race and must be ordered by
- * the caller.  Nothing in the array needs to start at zero. */
+ * the caller.  Nothing in the array needs to start at zero.  The dense bottom
+ * operator (dgmg_use_dense_bottom), when in use, and its partial sums are the
+ * context's own, allocated by dgmg_setup_levels. */
 dgmg_status dgmg_vcycle_noalloc(dgmg_ctx* ctx, const double* b, double* x, int nrhs);
 
 /* Solve A_L x = b by CG preconditioned with one V-cycle per iteration; FP64

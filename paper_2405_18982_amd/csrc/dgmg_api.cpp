@@ -197,6 +197,19 @@ struct dgmg_ctx {
   // device address of the library's scratch array on this context's device
   // (dgmg_vcycle_noalloc), looked up in dgmg_setup_levels
   void* scratch = nullptr;
+  // The V-cycle's bottom levels 0..dense_lvl (those the fused bottom launch
+  // runs) as a dense operator in the V-cycle precision, built at set-up from
+  // the bottom launch applied to unit vectors (row j = the operator's column
+  // j); applied with the scale dense_kappa / kappa (the V-cycle of kappa A_1
+  // is that of A_1 divided by kappa) to at most kDenseMaxRhs right-hand
+  // sides.  dense_part: the application's partial sums.
+  int dense_lvl = -1;
+  int dense_nd = 0;
+  double* dense64 = nullptr;
+  float* dense32 = nullptr;
+  void* dense_part = nullptr;
+  double dense_kappa = 1.0;
+  bool use_dense = true;
   std::string err;
 };
 
@@ -457,6 +470,19 @@ dgmg_status ensure_levels(dgmg_ctx* c, int upto) {
     if (s_ != DGMG_OK) return s_;          \
   } while (0)
 
+constexpr int kDenseMaxNd = 4096;  // largest bottom operator kept dense (134 MB in FP64)
+// most right-hand sides per dense application: the matrix is read once per
+// kDenseRhs of them, while the bottom launch runs all of them side by side
+// (one workgroup each) in about the time of one
+constexpr int kDenseMaxRhs = 16;
+
+template <typename T>
+T* dense_of(const dgmg_ctx* c);
+template <>
+double* dense_of<double>(const dgmg_ctx* c) { return c->dense64; }
+template <>
+float* dense_of<float>(const dgmg_ctx* c) { return c->dense32; }
+
 // Vectors of precision T on levels 0..L-1 (b, x) and the Full smoother's
 // second copies on levels 1..L (alt), for one V-cycle.
 template <typename T>
@@ -486,7 +512,10 @@ dgmg_status vcycle_T(dgmg_ctx* c, const T* bL, T* xL, int nrhs, const VBufs<T>* 
     RET(op_smooth<T>(c, l, X(l), B(l), 0, nrhs, true, Alt(l)));
     RET(op_restrict<T>(c, l, X(l), B(l), Bw(l - 1), nrhs));
   }
-  if (fuse3) {
+  if (fuse && c->use_dense && dense_of<T>(c) && c->dense_lvl == lo - 1 && nrhs <= kDenseMaxRhs) {
+    HIPCHK(c, dgmg::dense_apply<T>(dense_of<T>(c), c->dense_nd, B(lo - 1), X(lo - 1), nrhs,
+                                   (T)(c->dense_kappa / c->kappa), (T*)c->dense_part, c->stream));
+  } else if (fuse3) {
     const double s2 = level_scale(c, 2), s1 = level_scale(c, 1);
     HIPCHK(c, kset<T>(c).bottom3(tab_of<T>(c), c->variant, (T)s2, (T)(1.0 / s2), (T)s1, (T)(1.0 / s1),
                                  (T)(1.0 / level_scale(c, 0)), X(2), B(2), X(1), Bw(1), Bw(0), X(0),
@@ -541,6 +570,77 @@ dgmg_status precondition(dgmg_ctx* c, const double* r, double* z, int nrhs) {
   HIPCHK(c, dgmg::blas_f64_to_f32(r, T.b32, n, c->stream));
   RET(vcycle_T<float>(c, T.b32, T.x32, nrhs));
   HIPCHK(c, dgmg::blas_f32_to_f64(T.x32, z, n, c->stream));
+  return DGMG_OK;
+}
+
+// The bottom levels of the V-cycle as a dense operator (see dgmg_ctx): the
+// fused bottom launch applied to the nd unit vectors of level m gives the
+// operator's columns.  Only where that launch is used, level m lies below the
+// finest level and nd <= kDenseMaxNd; an allocation failure leaves the
+// context without it (the bottom launch stays in use).
+template <typename T>
+dgmg_status build_dense(dgmg_ctx* c) {
+  const bool fuse = c->fuse_bottom && kset<T>(c).bottom && c->variant != DGMG_SMOOTH_FULL;
+  if (!fuse) return DGMG_OK;
+  const bool fuse3 = c->fuse_bottom >= 2 && kset<T>(c).bottom3 && c->L >= 2;
+  const int m = fuse3 ? 2 : 1;
+  if (m >= c->L || c->lv[m].ndof > kDenseMaxNd) return DGMG_OK;
+  const int nd = (int)c->lv[m].ndof;
+  hipError_t e = hipSuccess;
+  std::vector<void*> tmp;
+  auto alloc = [&](long long count) -> T* {
+    if (e != hipSuccess) return nullptr;
+    T* p = dalloc<T>(count, e);
+    if (p) tmp.push_back(p);
+    return p;
+  };
+  auto release = [&]() {
+    for (void* p : tmp) hipFree(p);
+    tmp.clear();
+  };
+  T* Xm = alloc((long long)nd * nd);
+  T* Bm = alloc((long long)nd * nd);
+  T* bl[3] = {nullptr, nullptr, nullptr};
+  T* xl[3] = {nullptr, nullptr, nullptr};
+  for (int l = 0; l < m; ++l) {
+    bl[l] = alloc(c->lv[l].ndof * nd);
+    xl[l] = alloc(c->lv[l].ndof * nd);
+  }
+  T* part = alloc((long long)dgmg::kDenseChunks * kDenseMaxRhs * nd);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return DGMG_OK;
+  }
+  const double s1 = level_scale(c, 1);
+  e = dgmg::unit_batch<T>(Bm, nd, 0, nd, c->stream);
+  if (e == hipSuccess && fuse3) {
+    const double s2 = level_scale(c, 2);
+    e = kset<T>(c).bottom3(tab_of<T>(c), c->variant, (T)s2, (T)(1.0 / s2), (T)s1, (T)(1.0 / s1),
+                           (T)(1.0 / level_scale(c, 0)), Xm, Bm, xl[1], bl[1], bl[0], xl[0], nd,
+                           c->lv[2].ndof, c->lv[1].ndof, c->lv[0].ndof, c->stream);
+  } else if (e == hipSuccess) {
+    const int split = (c->fuse_bottom >= 2 && kset<T>(c).bottom_split) ? 1 : 0;
+    e = kset<T>(c).bottom(tab_of<T>(c), c->variant, split, (T)s1, (T)(1.0 / s1),
+                          (T)(1.0 / level_scale(c, 0)), Xm, Bm, bl[0], xl[0], nd, c->lv[1].ndof,
+                          c->lv[0].ndof, c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(c->stream);
+    release();
+    return fail(c, DGMG_ERR_HIP, std::string("dense bottom set-up: ") + hipGetErrorString(e));
+  }
+  // keep the operator and the partial sums, free the rest
+  for (void* p : tmp)
+    if (p != Xm && p != part) hipFree(p);
+  tmp.clear();
+  if (sizeof(T) == 8) c->dense64 = (double*)Xm;
+  else c->dense32 = (float*)Xm;
+  c->dense_part = part;
+  c->dense_lvl = m;
+  c->dense_nd = nd;
+  c->dense_kappa = c->kappa;
   return DGMG_OK;
 }
 
@@ -705,6 +805,8 @@ DGMG_API dgmg_status dgmg_setup_levels(dgmg_ctx* c, int vcycle_precision, int sm
   else RET(ensure_levels<float>(c, c->L));
   RET(ensure_alt<double>(c));
   if (vcycle_precision == DGMG_FP32) RET(ensure_alt<float>(c));
+  if (vcycle_precision == DGMG_FP64) RET(build_dense<double>(c));
+  else RET(build_dense<float>(c));
   return DGMG_OK;
 }
 
@@ -719,6 +821,18 @@ DGMG_API dgmg_status dgmg_use_graphs(dgmg_ctx* c, int enable) {
   c->use_graph = enable != 0;
   if (!c->use_graph) drop_graphs(c);
   return DGMG_OK;
+}
+
+DGMG_API dgmg_status dgmg_use_dense_bottom(dgmg_ctx* c, int enable) {
+  if (!c) return DGMG_ERR_ARG;
+  c->use_dense = enable != 0;
+  drop_graphs(c);  // graphs hold the previous bottom
+  return DGMG_OK;
+}
+
+DGMG_API int dgmg_dense_bottom_level(const dgmg_ctx* c) {
+  if (!c) return -1;
+  return (c->prec == 64 ? c->dense64 != nullptr : c->dense32 != nullptr) ? c->dense_lvl : -1;
 }
 
 DGMG_API dgmg_status dgmg_set_kappa(dgmg_ctx* c, double kappa) {
@@ -1401,6 +1515,9 @@ DGMG_API dgmg_status dgmg_destroy(dgmg_ctx* c) {
   }
   hipFree(c->tab64);
   hipFree(c->tab32);
+  hipFree(c->dense64);
+  hipFree(c->dense32);
+  hipFree(c->dense_part);
   hipFree(c->r);
   hipFree(c->z);
   hipFree(c->p);

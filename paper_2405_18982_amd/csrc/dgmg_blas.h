@@ -62,4 +62,17 @@ hipError_t blas_zero_f64(double* a, long long n, hipStream_t s);
 hipError_t blas_zero_f32(float* a, long long n, hipStream_t s);
 hipError_t blas_sub(const double* a, const double* b, double* y, long long n, hipStream_t s);
 
+// Dense operator of the V-cycle's bottom levels: y_r = sc * sum_j X[j][.]
+// b_r[j] for r < nrhs, X row-major nd x nd (row j = the operator's column j),
+// b and y [nrhs][nd]; deterministic (fixed chunks summed in order, in T).
+// part: kDenseChunks * nrhs * nd values of T.  X is read once per
+// kDenseRhs right-hand sides.
+constexpr int kDenseChunks = 8;
+constexpr int kDenseRhs = 8;
+template <typename T>
+hipError_t dense_apply(const T* X, int nd, const T* b, T* y, int nrhs, T sc, T* part, hipStream_t s);
+// b[r][i] = (i == r0 + r) for r < count: unit vectors r0 .. r0 + count - 1
+template <typename T>
+hipError_t unit_batch(T* b, int nd, int r0, int count, hipStream_t s);
+
 }  // namespace dgmg

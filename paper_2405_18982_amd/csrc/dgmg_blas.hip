@@ -235,6 +235,85 @@ int grid_for(long long n) {
   return (int)g;
 }
 
+// Dense operator y_r = sc * sum_j X[j][.] b_r[j] (X row-major nd x nd, row j
+// holding the operator's column j), in two deterministic stages.  j is cut
+// into kDenseChunks * kDenseWaves sub-chunks; block (64 outputs i, chunk c)
+// of a launch for right-hand sides r0 .. r0 + NR - 1 has one wave per
+// sub-chunk of chunk c, which sums it in j order with kDenseLoads rows of X
+// in flight per lane (b read by scalar loads: the wave index is made
+// wave-uniform so that the addresses are); the waves' sums are added in wave
+// order through LDS into part[c][r][i].  The second stage adds the chunks in
+// order and scales.  For nd = 4096 the first stage runs 16 waves per CU.
+constexpr int kDenseWaves = 8;
+constexpr int kDenseLoads = 16;
+template <typename T, int NR>
+__global__ void __launch_bounds__(64 * kDenseWaves)
+k_dense_part(const T* __restrict__ X, int nd, const T* __restrict__ b, int nrhs, int r0, T* __restrict__ part) {
+  __shared__ T red[kDenseWaves][NR][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ch = (nd + kDenseChunks * kDenseWaves - 1) / (kDenseChunks * kDenseWaves);
+  const int j0 = (blockIdx.y * kDenseWaves + w) * ch;
+  const int len = (j0 >= nd) ? 0 : (nd - j0 < ch ? nd - j0 : ch);
+  const int i = blockIdx.x * 64 + lane;
+  const T* __restrict__ xp = X + (long long)j0 * nd + (i < nd ? i : 0);
+  const T* __restrict__ bp = b + (long long)r0 * nd + j0;
+  T acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = T(0);
+  int jj = 0;
+  for (; jj + kDenseLoads <= len; jj += kDenseLoads) {
+    T xv[kDenseLoads];
+#pragma unroll
+    for (int u = 0; u < kDenseLoads; ++u) xv[u] = xp[(long long)(jj + u) * nd];
+#pragma unroll
+    for (int u = 0; u < kDenseLoads; ++u)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] += xv[u] * bp[(long long)r * nd + jj + u];
+  }
+  for (; jj < len; ++jj) {
+    const T xv = xp[(long long)jj * nd];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] += xv * bp[(long long)r * nd + jj];
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[w][r][lane] = acc[r];
+  __syncthreads();
+  const int r = threadIdx.x >> 6;
+  if (r < NR && i < nd) {
+    T sum = red[0][r][lane];
+#pragma unroll
+    for (int v = 1; v < kDenseWaves; ++v) sum += red[v][r][lane];
+    part[((long long)blockIdx.y * nrhs + r0 + r) * nd + i] = sum;
+  }
+}
+
+template <typename T, int NR>
+void launch_dense_part(const T* X, int nd, const T* b, int nrhs, int r0, T* part, hipStream_t s) {
+  const dim3 g((nd + 63) / 64, kDenseChunks);
+  hipLaunchKernelGGL((k_dense_part<T, NR>), g, dim3(64 * kDenseWaves), 0, s, X, nd, b, nrhs, r0, part);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+k_dense_sum(const T* __restrict__ part, int nd, int nrhs, T sc, T* __restrict__ y) {
+  const int i = blockIdx.x * kRedThreads + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= nd) return;
+  T sum = T(0);
+  for (int c = 0; c < kDenseChunks; ++c) sum += part[((long long)c * nrhs + r) * nd + i];
+  y[(long long)r * nd + i] = sc * sum;
+}
+
+// b[r][i] = (i == r0 + r): a batch of unit vectors
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+k_unit_batch(T* __restrict__ b, int nd, int r0) {
+  const int i = blockIdx.x * kRedThreads + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i < nd) b[(long long)r * nd + i] = (i == r0 + r) ? T(1) : T(0);
+}
+
 }  // namespace
 
 hipError_t blas_dot2(const double* a, const double* b, const double* c, const double* d,
@@ -340,6 +419,38 @@ hipError_t blas_zero_f32(float* a, long long n, hipStream_t s) {
   hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(n)), dim3(kRedThreads), 0, s, a, 0.0f, n);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t dense_apply(const T* X, int nd, const T* b, T* y, int nrhs, T sc, T* part, hipStream_t s) {
+  if (nd <= 0 || nrhs <= 0) return hipErrorInvalidValue;
+  for (int r0 = 0; r0 < nrhs; r0 += kDenseRhs) {
+    switch (nrhs - r0 < kDenseRhs ? nrhs - r0 : kDenseRhs) {
+      case 1: launch_dense_part<T, 1>(X, nd, b, nrhs, r0, part, s); break;
+      case 2: launch_dense_part<T, 2>(X, nd, b, nrhs, r0, part, s); break;
+      case 3: launch_dense_part<T, 3>(X, nd, b, nrhs, r0, part, s); break;
+      case 4: launch_dense_part<T, 4>(X, nd, b, nrhs, r0, part, s); break;
+      case 5: launch_dense_part<T, 5>(X, nd, b, nrhs, r0, part, s); break;
+      case 6: launch_dense_part<T, 6>(X, nd, b, nrhs, r0, part, s); break;
+      case 7: launch_dense_part<T, 7>(X, nd, b, nrhs, r0, part, s); break;
+      default: launch_dense_part<T, 8>(X, nd, b, nrhs, r0, part, s); break;
+    }
+  }
+  const dim3 g2((nd + kRedThreads - 1) / kRedThreads, nrhs);
+  hipLaunchKernelGGL((k_dense_sum<T>), g2, dim3(kRedThreads), 0, s, part, nd, nrhs, sc, y);
+  return hipGetLastError();
+}
+template hipError_t dense_apply<double>(const double*, int, const double*, double*, int, double, double*,
+                                        hipStream_t);
+template hipError_t dense_apply<float>(const float*, int, const float*, float*, int, float, float*, hipStream_t);
+
+template <typename T>
+hipError_t unit_batch(T* b, int nd, int r0, int count, hipStream_t s) {
+  const dim3 g((nd + kRedThreads - 1) / kRedThreads, count);
+  hipLaunchKernelGGL((k_unit_batch<T>), g, dim3(kRedThreads), 0, s, b, nd, r0);
+  return hipGetLastError();
+}
+template hipError_t unit_batch<double>(double*, int, int, int, hipStream_t);
+template hipError_t unit_batch<float>(float*, int, int, int, hipStream_t);
 
 hipError_t blas_sub(const double* a, const double* b, double* y, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(kRedThreads), 0, s, a, b, y, n);

@@ -30,6 +30,8 @@ SIGNATURES = {
     "dgmg_set_stream": (_I, [_P, _P]),
     "dgmg_set_kappa": (_I, [_P, _D]),
     "dgmg_use_graphs": (_I, [_P, _I]),
+    "dgmg_use_dense_bottom": (_I, [_P, _I]),
+    "dgmg_dense_bottom_level": (_I, [_P]),
     "dgmg_level_ndofs": (_LL, [_P, _I]),
     "dgmg_level_cells": (_I, [_P, _I]),
     "dgmg_finest_level": (_I, [_P]),
@@ -188,6 +190,15 @@ class Problem:
 
     def use_graphs(self, enable=True):
         self._check(lib().dgmg_use_graphs(self._ctx, int(bool(enable))))
+
+    def use_dense_bottom(self, enable=True):
+        """V-cycle bottom levels as the dense operator built at set-up (True)
+        or as the fused bottom launch (False)."""
+        self._check(lib().dgmg_use_dense_bottom(self._ctx, int(bool(enable))))
+
+    def dense_bottom_level(self):
+        """Level whose correction the dense bottom operator gives, or -1."""
+        return int(lib().dgmg_dense_bottom_level(self._ctx))
 
     def set_kappa(self, kappa):
         self.kappa = float(kappa)

@@ -88,6 +88,13 @@ def smooth_step_counts(dim, k, N, nrhs=1, s=8):
     return tot
 
 
+def dense_bottom_counts(nd, nrhs=1, s=8):
+    """The V-cycle's bottom levels applied as their dense nd x nd operator:
+    the matrix read once, b read and x written; one multiply-add per matrix
+    entry and right-hand side."""
+    return dict(bytes=s * (nd * nd + 2 * nd * nrhs), flops=2 * nd * nd * nrhs)
+
+
 def bound(counts, seconds, precision=64):
     """Roofline position of a measured launch: achieved GB/s and GFLOP/s, the
     binding resource (larger ideal time) and the fraction of its peak."""

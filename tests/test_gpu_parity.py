@@ -362,6 +362,7 @@ def test_fused_vcycle_bottom_equals_separate_kernels(monkeypatch, dim, k, L, pre
     for fuse in ("2", "1", "0"):
         monkeypatch.setenv("DGMG_FUSE_BOTTOM", fuse)
         prob = dgmg.Problem(dim, k, L, precision=precision, variant=variant, nrhs_max=2)
+        prob.use_dense_bottom(False)
         B = inputs.uniform(33, (2, prob.ndofs()))
         dt = torch.float64 if precision == 64 else torch.float32
         res = [prob.vcycle(cuda(B, dt)).clone()]
@@ -372,3 +373,86 @@ def test_fused_vcycle_bottom_equals_separate_kernels(monkeypatch, dim, k, L, pre
     torch.cuda.synchronize()
     for a, b, c in zip(outs["2"], outs["1"], outs["0"]):
         assert torch.equal(a, c) and torch.equal(b, c)
+
+
+MODES = {0: "exact", 1: "local", 2: "full", 3: "clamped"}
+
+
+@pytest.mark.parametrize("dim,k,L,precision,variant,level", [
+    (3, 3, 2, 64, 0, 1), (3, 3, 2, 32, 1, 1), (3, 3, 2, 64, 3, 1), (3, 2, 3, 64, 0, 1),
+    (3, 1, 2, 32, 0, 1), (2, 5, 3, 64, 0, 2), (2, 7, 3, 32, 3, 2), (2, 3, 4, 64, 1, 2),
+    (3, 4, 2, 64, 0, -1), (2, 3, 2, 64, 0, -1), (3, 3, 2, 64, 2, -1)])
+def test_dense_bottom_equals_bottom_launch(dim, k, L, precision, variant, level):
+    """The V-cycle with its bottom levels as the dense operator built at
+    set-up equals the V-cycle with the fused bottom launch up to rounding
+    order, and the oracle's V-cycle; also after a change of kappa (the
+    operator is scaled, not rebuilt).  Where no operator is built (bottom
+    level too large, the bottom level is the finest, Full smoother) both
+    switches give the launch bitwise."""
+    note(f"dense bottom d={dim} k={k} L={L} fp{precision} variant={variant}")
+    prob = dgmg.Problem(dim, k, L, precision=precision, variant=variant, nrhs_max=3)
+    assert prob.dense_bottom_level() == level
+    dt = torch.float64 if precision == 64 else torch.float32
+    B = inputs.uniform(34, (3, prob.ndofs()))
+    tol = 1e-13 if precision == 64 else 1e-5
+    for kappa in (1.0, 0.37):
+        prob.set_kappa(kappa)
+        got = {}
+        for dense in (True, False):
+            prob.use_dense_bottom(dense)
+            got[dense] = host(prob.vcycle(cuda(B, dt)))
+        if level < 0:
+            assert np.array_equal(got[True], got[False])
+        else:
+            close(got[True], got[False], rtol=tol, mtol=10 * tol)
+        H = Hierarchy(dim, k, L, inputs.sigma_of(k), kappa=kappa, mode=MODES[variant])
+        ref = H.vcycle(B[1])
+        close(got[True][1], ref, rtol=1e-11 if precision == 64 else 1e-5,
+              mtol=1e-10 if precision == 64 else 1e-4)
+    prob.close()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_dense_bottom_many_rhs(precision):
+    """Up to 16 right-hand sides take the dense bottom (11: two groups of 8,
+    the second ragged), each equal to its single-RHS V-cycle up to rounding
+    order; 17 take the bottom launch, bitwise as with the matrix switched
+    off."""
+    note(f"dense bottom many rhs fp{precision}")
+    prob = dgmg.Problem(3, 3, 2, precision=precision, nrhs_max=17)
+    assert prob.dense_bottom_level() == 1
+    dt = torch.float64 if precision == 64 else torch.float32
+    tol = 1e-13 if precision == 64 else 1e-5
+    B = inputs.uniform(36, (17, prob.ndofs()))
+    X11 = host(prob.vcycle(cuda(B[:11], dt)))
+    for j in (0, 7, 8, 10):
+        close(X11[j], host(prob.vcycle(cuda(B[j], dt))), rtol=tol, mtol=10 * tol)
+    prob.use_dense_bottom(False)
+    L11 = host(prob.vcycle(cuda(B[:11], dt)))
+    close(X11, L11, rtol=tol, mtol=10 * tol)
+    L17 = host(prob.vcycle(cuda(B, dt)))
+    prob.use_dense_bottom(True)
+    assert np.array_equal(host(prob.vcycle(cuda(B, dt))), L17)
+    prob.close()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_dense_bottom_in_graph_and_noalloc(precision):
+    """CG with the dense bottom in the captured V-cycle equals CG with eager
+    launches bitwise, and the allocation-free V-cycle uses the same bottom."""
+    note(f"dense bottom graph fp{precision}")
+    prob = dgmg.Problem(3, 3, 2, precision=precision, nrhs_max=2)
+    assert prob.dense_bottom_level() == 1
+    B = inputs.uniform(35, (2, prob.ndofs()))
+    res = {}
+    for graphs in (True, False):
+        prob.use_graphs(graphs)
+        x, it, _ = prob.solve(cuda(B), rtol=1e-10, maxit=100)
+        res[graphs] = (host(x), list(it))
+    assert res[True][1] == res[False][1]
+    assert np.array_equal(res[True][0], res[False][0])
+    a = host(prob.vcycle(cuda(B)))
+    out = torch.empty((2, prob.ndofs()), dtype=torch.float64, device="cuda")
+    prob.vcycle_noalloc(cuda(B), out)
+    assert np.array_equal(a, host(out))
+    prob.close()

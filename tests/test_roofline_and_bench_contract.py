@@ -75,6 +75,16 @@ def test_bound_picks_the_slower_resource():
     assert abs(r32["frac"] - 10.0 / roofline.PEAK_FP32_TFLOPS) < 1e-12
 
 
+def test_dense_bottom_counts():
+    # 3-D Q3: level 1 has 4^3 cells of 4^3 nodes, the operator 4096 x 4096
+    nd = 4 ** 3 * 4 ** 3
+    c = roofline.dense_bottom_counts(nd)
+    assert c["bytes"] == 8 * nd * nd + 16 * nd and c["flops"] == 2 * nd * nd
+    assert roofline.bound(c, 20e-6)["bound"] == "hbm"  # 1/4 flop per byte
+    c3 = roofline.dense_bottom_counts(nd, nrhs=3, s=4)
+    assert c3["bytes"] == 4 * (nd * nd + 6 * nd) and c3["flops"] == 6 * nd * nd
+
+
 def test_bench_refuses_more_than_one_gpu():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, cwd=ROOT, timeout=120)
