@@ -670,39 +670,62 @@ __device__ __forceinline__ Sides<T> yline_sides(const Tab<K, T>* __restrict__ t,
 // Sides of the smoother's y-line (px, pz): the traces of the y-neighbours at
 // nodes (a, k or 0, pz), a in the cell block of px, contracted with M_x
 // straight from global memory (n contiguous values per side).  MODE 2 (the
-// paper's Dirichlet residual) ignores interior neighbours.
+// paper's Dirichlet residual) ignores interior neighbours.  Split into the
+// loads (yside_load: the mass row and both neighbours' n traces, the patch's
+// own cells standing in for a missing neighbour, whose values go unused) and
+// the arithmetic (yside_finish), so that callers can issue the loads together
+// with their other global loads.
+template <typename T>
+struct YSideRaw {
+  T row[n], l[n], r[n];
+};
 template <typename T, int MODE>
-__device__ __forceinline__ Sides<T> yline_sides_global(const Tab<K, T>* __restrict__ t,
-                                                       const T* __restrict__ x, int N,
-                                                       const PatchPos& P, int px, int pz) {
+__device__ __forceinline__ void yside_load(const T* __restrict__ x, int N, const PatchPos& P, int px, int pz,
+                                           YSideRaw<T>& y) {
+  if (MODE == 2) return;
+  const int cx = P.lo[0] + px / n;
+  const int cz = (D == 3) ? P.lo[2] + pz / n : 0;
+  const int az = (D == 3) ? pz % n : 0;
+  const bool bl = (P.lo[1] == 0), br = (P.lo[1] + 1 == N - 1);
+  mass_row<T>(px % n, y.row);
+  const T* rl = x + cell_index(N, cx, bl ? P.lo[1] : P.lo[1] - 1, cz) * NC + K * n + az * n * n;
+  const T* rr = x + cell_index(N, cx, br ? P.lo[1] + 1 : P.lo[1] + 2, cz) * NC + az * n * n;
+#pragma unroll
+  for (int nu = 0; nu < n; ++nu) {
+    y.l[nu] = rl[nu];
+    y.r[nu] = rr[nu];
+  }
+}
+template <typename T, int MODE>
+__device__ __forceinline__ Sides<T> yside_finish(const YSideRaw<T>& y, int N, const PatchPos& P) {
   Sides<T> sd;
   sd.bl = (P.lo[1] == 0);
   sd.br = (P.lo[1] + 1 == N - 1);
   sd.aL = sd.bL = sd.aR = sd.bR = T(0);
   sd.lit = (MODE == 2);
   if (MODE == 2) return sd;
-  const int mu = px % n;
-  const int cx = P.lo[0] + px / n;
-  const int cz = (D == 3) ? P.lo[2] + pz / n : 0;
-  const int az = (D == 3) ? pz % n : 0;
   const T half = T(0.5);
-  T row[n];
-  if (!sd.bl || !sd.br) mass_row<T>(mu, row);
   if (!sd.bl) {
-    const T* r = x + cell_index(N, cx, P.lo[1] - 1, cz) * NC + K * n + az * n * n;
     T s = T(0);
 #pragma unroll
-    for (int nu = 0; nu < n; ++nu) s += row[nu] * r[nu];
+    for (int nu = 0; nu < n; ++nu) s += y.row[nu] * y.l[nu];
     sd.bL = -half * s;
   }
   if (!sd.br) {
-    const T* r = x + cell_index(N, cx, P.lo[1] + 2, cz) * NC + az * n * n;
     T s = T(0);
 #pragma unroll
-    for (int nu = 0; nu < n; ++nu) s += row[nu] * r[nu];
+    for (int nu = 0; nu < n; ++nu) s += y.row[nu] * y.r[nu];
     sd.bR = half * s;
   }
   return sd;
+}
+template <typename T, int MODE>
+__device__ __forceinline__ Sides<T> yline_sides_global(const Tab<K, T>* __restrict__ t,
+                                                       const T* __restrict__ x, int N,
+                                                       const PatchPos& P, int px, int pz) {
+  YSideRaw<T> y;
+  yside_load<T, MODE>(x, N, P, px, pz, y);
+  return yside_finish<T, MODE>(y, N, P);
 }
 
 // In the y-phase the z-face arrays are contracted along x in place (lines at
@@ -746,6 +769,32 @@ __device__ __forceinline__ Sides<T> zline_sides(const Tab<K, T>* __restrict__ t,
   } else {
     if (!sd.bl) sd.bL = ext_my<T>(t, z + 0 * NF, px, py);
     if (!sd.br) sd.bR = ext_my<T>(t, z + 1 * NF, px, py);
+  }
+  return sd;
+}
+
+// zline_sides with NCOMP = 1 and the mass row of py (M[py % n][.]) given
+// (loaded by the caller with its other global loads); same arithmetic.
+template <typename T>
+__device__ __forceinline__ Sides<T> zline_sides_row(const T (&row)[n], const T* ext, int N, const PatchPos& P,
+                                                    int px, int py) {
+  Sides<T> sd;
+  sd.bl = (P.lo[2] == 0);
+  sd.br = (P.lo[2] + 1 == N - 1);
+  sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  sd.lit = false;
+  const int c0 = (py / n) * n;
+  if (!sd.bl) {
+    T s = T(0);
+#pragma unroll
+    for (int nu = 0; nu < n; ++nu) s += row[nu] * ext[px + E * (c0 + nu)];
+    sd.bL = s;
+  }
+  if (!sd.br) {
+    T s = T(0);
+#pragma unroll
+    for (int nu = 0; nu < n; ++nu) s += row[nu] * ext[NF + px + E * (c0 + nu)];
+    sd.bR = s;
   }
   return sd;
 }
@@ -860,6 +909,25 @@ __device__ __forceinline__ Sides<T> rfz_sides(int N, const PatchPos& P, int lane
   return sd;
 }
 
+// rfz_sides with traces, the mass row of py = lane / E given (loaded by the
+// caller with its other global loads); same arithmetic
+template <typename T>
+__device__ __forceinline__ Sides<T> rfz_sides_row(const T (&rowy)[n], int N, const PatchPos& P, int lane, T wz0,
+                                                  T wz1) {
+  Sides<T> sd;
+  sd.bl = (P.lo[2] == 0);
+  sd.br = (P.lo[2] + 1 == N - 1);
+  sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  sd.lit = false;
+  const int py = lane / E;
+  const int wl = threadIdx.x & 63;
+  const T zL = ycontract_lanes<T>(rowy, wz0, wl, py % n);
+  const T zR = ycontract_lanes<T>(rowy, wz1, wl, py % n);
+  if (!sd.bl) sd.bL = zL;
+  if (!sd.br) sd.bR = zR;
+  return sd;
+}
+
 // Operator passes of y = A_ref x on the patch.  Phase X0 reads the x-lines
 // from global (and keeps them in xl for the caller), gathers the y/z face
 // data; the last pass (z in 3-D, y in 2-D) hands each output line to
@@ -869,8 +937,7 @@ __device__ __forceinline__ Sides<T> rfz_sides(int N, const PatchPos& P, int lane
 template <typename T, int MODE, bool RFA = false, typename Emit>
 __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t, const T* __restrict__ x,
                                                 int N, const PatchPos& P, T* A, T* B, T* ext,
-                                                int lane, bool active, Line<T>& xl,
-                                                const Sides<T>& ysd_global, Emit emit) {
+                                                int lane, bool active, Line<T>& xl, Emit emit) {
   constexpr int NCOMP = (MODE == 0) ? 2 : 1;
   // Dirichlet smoothers on patches of one wave: the z-face traces go through
   // registers, not LDS.  Lane (px, py) reads the n traces of its x-block on
@@ -888,8 +955,77 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
   const bool n0x = MODE == 0 || (P.ty[0] & 1), nEx = MODE == 0 || (P.ty[0] & 2);
   const bool n0y = MODE == 0 || (P.ty[1] & 1), nEy = MODE == 0 || (P.ty[1] & 2);
   const bool n0z = MODE == 0 || (P.ty[2] & 1), nEz = MODE == 0 || (P.ty[2] & 2);
+  // smoothers: y-face sides of the lane's y-line straight from global, and
+  // (RFZ) the mass row of the z-line's py for the Z pass
+  Sides<T> ysd_global{};
+  T rowz[n];
   // X0: a = M_x x -> A, b = L_x x -> B
-  if (active) {
+  if (active && MODE != 0 && NL == TPP) {
+    // Smoothers with one line per lane: every global load of the pass is
+    // issued before any of the values is used (one memory round trip instead
+    // of one per helper), then the arithmetic of yline_sides_global,
+    // rfz_traces and xline_sides in their order.
+    const int px = lane % E, q = lane / E;  // y-line (px, pz = q), z-face node (px, py = q)
+    YSideRaw<T> yraw;
+    yside_load<T, MODE>(x, N, P, px, (D == 3) ? q : 0, yraw);
+    T zl[n], zr[n];
+    if constexpr (RFZ && MODE == 1) {
+      const int cx = P.lo[0] + px / n, cy = P.lo[1] + q / n;
+      const long long o = (long long)n * (q % n);
+      const T* cl = x + cell_index(N, cx, cy, P.lo[2] > 0 ? P.lo[2] - 1 : P.lo[2]) * NC + o + K * n * n;
+      const T* cr = x + cell_index(N, cx, cy, P.lo[2] + 2 < N ? P.lo[2] + 2 : P.lo[2]) * NC + o;
+#pragma unroll
+      for (int nu = 0; nu < n; ++nu) {
+        zl[nu] = cl[nu];
+        zr[nu] = cr[nu];
+      }
+      mass_row<T>(q % n, rowz);
+    }
+    const int py = lane % E, pz = lane / E;
+    const long long row0 = xrow_offset(N, P, py, pz);
+    read_xline<T>(x, row0, xl);
+    const bool xbl = (P.lo[0] == 0), xbr = (P.lo[0] + 1 == N - 1);
+    T xtl = T(0), xtr = T(0);
+    if (MODE != 2) {
+      xtl = x[xbl ? row0 : row0 - NC + K];
+      xtr = x[xbr ? row0 : row0 + 2 * NC];
+    }
+    ysd_global = yside_finish<T, MODE>(yraw, N, P);
+    if constexpr (RFZ && MODE == 1) {
+      const T half = T(0.5);
+      if (P.lo[2] > 0) {
+        T s = T(0);
+#pragma unroll
+        for (int nu = 0; nu < n; ++nu) s += yraw.row[nu] * (-half * zl[nu]);
+        wz0 = s;
+      }
+      if (P.lo[2] + 2 < N) {
+        T s = T(0);
+#pragma unroll
+        for (int nu = 0; nu < n; ++nu) s += yraw.row[nu] * (half * zr[nu]);
+        wz1 = s;
+      }
+    } else if constexpr (!RFZ) {
+      gather_ext<T, MODE>(t, x, N, P, lane, ext);
+    }
+    Sides<T> sd;
+    sd.bl = xbl;
+    sd.br = xbr;
+    sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+    sd.lit = (MODE == 2);
+    if (MODE != 2) {
+      if (!sd.bl) sd.bL = -T(0.5) * xtl;
+      if (!sd.br) sd.bR = T(0.5) * xtr;
+    }
+    int base, stride;
+    line_geom(0, lane, base, stride);
+    Line<T> a, b;
+    line_mass<T>(t, xl, a, n0x, nEx);
+    line_sipg<T, false>(t, xl, sd, b, n0x, nEx);
+    store_line(A, base, stride, a);
+    store_line(B, base, stride, b);
+  } else if (active) {
+    if constexpr (MODE != 0) ysd_global = yline_sides_global<T, MODE>(t, x, N, P, lane % E, lane / E);
     if constexpr (RFZ) {
       if constexpr (MODE == 1) rfz_traces<T>(x, N, P, lane, wz0, wz1);
     } else if constexpr (RFA) {
@@ -965,7 +1101,9 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
         load_line(B, base, stride, c);
         load_line(A, base, stride, d);
         Sides<T> sd;
-        if constexpr (RFZ) {
+        if constexpr (RFZ && MODE == 1 && NL == TPP) {
+          sd = rfz_sides_row<T>(rowz, N, P, i, wz0, wz1);
+        } else if constexpr (RFZ) {
           sd = rfz_sides<T, MODE == 1>(N, P, i, wz0, wz1);
         } else if constexpr (RFA) {
           T rowy[n];
@@ -1051,8 +1189,7 @@ k_apply(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restri
   T* yr = y + roff;
   const PatchPos P = patch_pos(g, active ? pid : 0);
   Line<T> xl;
-  Sides<T> ysd{};
-  operator_passes<T, 0>(t, xr, g.N, P, A, B, ext, lane, active, xl, ysd,
+  operator_passes<T, 0>(t, xr, g.N, P, A, B, ext, lane, active, xl,
                         [&](int, int base, int stride, const Line<T>& v) {
 #pragma unroll
                           for (int p = 0; p < E; ++p) A[base + p * stride] = scale * v.v[p];
@@ -1379,13 +1516,11 @@ __device__ __forceinline__ void smooth_body(const Tab<K, T>* __restrict__ t, con
         store_line(A, base, stride, o);
       }
   } else {
-    const Sides<T> ysd = (!FULL && active) ? yline_sides_global<T, OPM>(t, xr, g.N, P, lane % E, lane / E)
-                                           : Sides<T>{};
     Line<T> bline;
     if (PREFETCH && active) read_lastline<T>(br, g.N, P, lane, bline);
 
     // residual r = b - A x on the last pass, contracted with S^T of that direction
-    operator_passes<T, OPM>(t, xr, g.N, P, A, B, ext, lane, active, xl, ysd,
+    operator_passes<T, OPM>(t, xr, g.N, P, A, B, ext, lane, active, xl,
                             [&](int l, int base, int stride, const Line<T>& v) {
                               Line<T> r, o;
                               if (PREFETCH) r = bline;
@@ -1760,30 +1895,52 @@ __device__ __forceinline__ void smooth_split_body(const Tab<K, T>* __restrict__ 
     }
     __syncthreads();
   } else {
-    const Sides<T> ysd = active ? yline_sides_global<T, OPM>(t, xr, g.N, P, lane % E, lane / E) : Sides<T>{};
+    // Every global load of the first phases is issued here, before any of
+    // the values is used (one memory round trip instead of one per helper):
+    // the y-neighbour traces with their mass row, this lane's z-face trace,
+    // the x-line with its x-neighbour traces and the mass row of the z-sides.
+    static_assert(TPP == NF, "one z-face trace per lane of the two waves");
+    YSideRaw<T> yraw;
+    T ztr = T(0), xtl = T(0), xtr = T(0);
+    T zrow[n];
+    Line<T> xl;
+    const int zf = lane, zside = H;  // this lane's z-face entry (face node, side)
+    const int znb = (zside == 0) ? P.lo[2] - 1 : P.lo[2] + 2;
+    const bool zhas = MODE == 1 && znb >= 0 && znb < g.N;
+    const int py = lane % E, pz = lane / E;
+    const long long row0 = xrow_offset(g.N, P, py, pz);
+    const bool xbl = (P.lo[0] == 0), xbr = (P.lo[0] + 1 == g.N - 1);
+    if (active) {
+      yside_load<T, OPM>(xr, g.N, P, lane % E, lane / E, yraw);
+      if (MODE == 1) {
+        const int a = zf % E, bb = zf / E;
+        const long long base = cell_index(g.N, P.lo[0] + a / n, P.lo[1] + bb / n, zhas ? znb : P.lo[2]) * NC +
+                               a % n + n * (bb % n);
+        ztr = xr[base + (long long)((zside == 0) ? K : 0) * n * n];
+      }
+      read_xline<T>(xr, row0, xl);
+      if (OPM != 2) {
+        xtl = xr[xbl ? row0 : row0 - NC + K];
+        xtr = xr[xbr ? row0 : row0 + 2 * NC];
+      }
+      mass_row<T>((lane / E) % n, zrow);
+    }
+    const Sides<T> ysd = active ? yside_finish<T, OPM>(yraw, g.N, P) : Sides<T>{};
     // X0: a = M_x x, b = L_x x on this half -> A, B
     if (active) {
       // z-face traces, spread over both waves (the register form of the
       // one-wave kernel measured slower here: both waves would repeat it)
-      for (int i = lane + H * TPP; i < 2 * NF; i += 2 * TPP) {
-        const int f = i % NF;
-        const int side = i / NF;
-        const int nb = (side == 0) ? P.lo[2] - 1 : P.lo[2] + 2;
-        T beta = T(0);
-        if (MODE == 1 && nb >= 0 && nb < g.N) {
-          const int a = f % E, bb = f / E;
-          const long long base = cell_index(g.N, P.lo[0] + a / n, P.lo[1] + bb / n, nb) * NC + a % n +
-                                 n * (bb % n);
-          const T tr = xr[base + (long long)((side == 0) ? K : 0) * n * n];
-          beta = (side == 0) ? -T(0.5) * tr : T(0.5) * tr;
-        }
-        ext[side * NF + f] = beta;
+      ext[zside * NF + zf] = zhas ? ((zside == 0) ? -T(0.5) * ztr : T(0.5) * ztr) : T(0);
+      // x-sides as xline_sides forms them for the smoother's residual
+      Sides<T> sd;
+      sd.bl = xbl;
+      sd.br = xbr;
+      sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+      sd.lit = (OPM == 2);
+      if (OPM != 2) {
+        if (!sd.bl) sd.bL = -T(0.5) * xtl;
+        if (!sd.br) sd.bR = T(0.5) * xtr;
       }
-      const int py = lane % E, pz = lane / E;
-      const long long row0 = xrow_offset(g.N, P, py, pz);
-      Line<T> xl;
-      read_xline<T>(xr, row0, xl);
-      const Sides<T> sd = xline_sides<T, OPM>(t, xr, g.N, P, row0);
 #pragma unroll
       for (int j = 0; j < n; ++j) xh.v[j] = xl.v[H * n + j];
       int base, stride;
@@ -1826,7 +1983,7 @@ __device__ __forceinline__ void smooth_split_body(const Tab<K, T>* __restrict__ 
       Line<T> cl, dl;
       load_line(B, base, stride, cl);
       load_line(A, base, stride, dl);
-      Sides<T> sd = zline_sides<T, 1>(t, ext, g.N, P, px, py);
+      Sides<T> sd = zline_sides_row<T>(zrow, ext, g.N, P, px, py);
       sd.lit = (OPM == 2);
       Half<T> y;
       half_mass<T, H>(cl, y, endz);
@@ -1963,8 +2120,7 @@ __device__ __forceinline__ void restrict_body(const Tab<K, T>* __restrict__ t, c
   const long long roff = (long long)rhs * ndof;
   const PatchPos P = patch_pos(g, active ? pid : 0);
   Line<T> xl;
-  Sides<T> ysd{};
-  operator_passes<T, 0, kRestrictRF>(t, x + roff, g.N, P, A, B, ext, lane, active, xl, ysd,
+  operator_passes<T, 0, kRestrictRF>(t, x + roff, g.N, P, A, B, ext, lane, active, xl,
                         [&](int l, int base, int stride, const Line<T>& v) {
                           Line<T> r;
                           read_lastline<T>(b + roff, g.N, P, l, r);
