@@ -514,6 +514,36 @@ __device__ __forceinline__ long long xrow_offset(int N, const PatchPos& P, int p
   return node_offset(N, P, 0, py, (D == 3) ? pz : 0);
 }
 
+// Side flags and x-face couplings of an x-line for the full operator from the
+// n values of the rows of its outside x-neighbours (rl: the cell below, rr:
+// the cell above; ignored on boundary sides).
+template <typename T>
+__device__ __forceinline__ Sides<T> xsides_rows(T sg, bool bl, bool br, const T (&rl)[n], const T (&rr)[n]) {
+  const T half = T(0.5);
+  Sides<T> sd;
+  sd.bl = bl;
+  sd.br = br;
+  sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  sd.lit = false;
+  if (!sd.bl) {
+    const T tr = rl[K];
+    sd.bL = -half * tr;
+    T g = T(0);
+#pragma unroll
+    for (int j = 0; j < n; ++j) g += T(kRef.d1[j]) * rl[j];
+    sd.aL = half * g - sg * tr;
+  }
+  if (!sd.br) {
+    const T tr = rr[0];
+    sd.bR = half * tr;
+    T g = T(0);
+#pragma unroll
+    for (int j = 0; j < n; ++j) g += T(kRef.d0[j]) * rr[j];
+    sd.aR = -sg * tr - half * g;
+  }
+  return sd;
+}
+
 // Side flags and x-face couplings of x-line (py, pz), read from the rows of
 // the outside neighbours.  MODE 0: full operator rows; 1: smoother (only the
 // traces matter, alpha acts on dropped rows); 2: the paper's Dirichlet
@@ -823,31 +853,36 @@ __device__ __forceinline__ T ycontract_lanes(const T (&row)[n], T v, int wl, int
   return s;
 }
 
+// Couplings (alpha, beta) of one face node of a neighbour cell across a y-
+// or z-face from the node's n values along the normal, v[j] (SIDE 0: the
+// neighbour below, read at its far end; SIDE 1: above, read at its near end).
+template <typename T, int SIDE>
+__device__ __forceinline__ void face_node(T sg, const T (&v)[n], T& al, T& be) {
+  const T half = T(0.5);
+  T g = T(0), tr = T(0);
+#pragma unroll
+  for (int j = 0; j < n; ++j) {
+    g += (SIDE == 0 ? T(kRef.d1[j]) : T(kRef.d0[j])) * v[j];
+    if (j == (SIDE == 0 ? K : 0)) tr = v[j];
+  }
+  al = (SIDE == 0) ? (half * g - sg * tr) : (-sg * tr - half * g);
+  be = (SIDE == 0) ? -half * tr : half * tr;
+}
+
 // Couplings of the n face nodes nu of an x-block of a neighbour cell across
-// a y- or z-face (SIDE 0: the neighbour below, read at its far end; SIDE 1:
-// above, read at its near end); node nu, normal index j sits at
-// c[nu + j strideN].  a = sum_nu row[nu] alpha(nu), b = sum_nu row[nu] beta(nu).
+// a y- or z-face; node nu, normal index j sits at c[nu + j strideN].
+// a = sum_nu row[nu] alpha(nu), b = sum_nu row[nu] beta(nu).
 template <typename T, int SIDE>
 __device__ __forceinline__ void face_pair(const Tab<K, T>* __restrict__ t, const T* __restrict__ c,
                                           int strideN, const T (&row)[n], T& a, T& b) {
-  const T half = T(0.5);
   const T sg = t->sigma;
-  // row by row along the normal (n accumulators live, not n^2 values)
-  T g[n], tr[n], al[n], be[n];
-#pragma unroll
-  for (int nu = 0; nu < n; ++nu) g[nu] = T(0);
-#pragma unroll
-  for (int j = 0; j < n; ++j)
-#pragma unroll
-    for (int nu = 0; nu < n; ++nu) {
-      const T v = c[nu + j * strideN];
-      g[nu] += (SIDE == 0 ? T(kRef.d1[j]) : T(kRef.d0[j])) * v;
-      if (j == (SIDE == 0 ? K : 0)) tr[nu] = v;
-    }
+  T al[n], be[n];
 #pragma unroll
   for (int nu = 0; nu < n; ++nu) {
-    al[nu] = (SIDE == 0) ? (half * g[nu] - sg * tr[nu]) : (-sg * tr[nu] - half * g[nu]);
-    be[nu] = (SIDE == 0) ? -half * tr[nu] : half * tr[nu];
+    T v[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j) v[j] = c[nu + j * strideN];
+    face_node<T, SIDE>(sg, v, al[nu], be[nu]);
   }
   T sa = T(0), sb = T(0);
 #pragma unroll
@@ -856,6 +891,47 @@ __device__ __forceinline__ void face_pair(const Tab<K, T>* __restrict__ t, const
   for (int nu = 0; nu < n; ++nu) sb += row[nu] * be[nu];
   a = sa;
   b = sb;
+}
+
+// The lanes of an x-block (n consecutive lanes of a row of E) lie in one wave
+// where E divides 64 (3-D Q1, Q3, Q7).
+constexpr bool kXShfl = (64 % E) == 0;
+
+// sum_nu row[nu] v(lane of node nu in this lane's x-block): the mass
+// contraction of per-node face values held one per lane (wl: the lane's index
+// in its wave, nuo: its node in the block); every lane of the block takes part
+// Node NU of this lane's x-block, read by a DPP quad permutation (x-blocks of
+// 2 or 4 lanes lie in one quad): a VALU move per 32 bits, no LDS crossbar.
+template <int NU>
+__device__ __forceinline__ constexpr int xblock_dpp() {
+  return (n == 4) ? NU * 0x55 : (NU | (NU << 2) | ((2 + NU) << 4) | ((2 + NU) << 6));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <typename T>
+__device__ __forceinline__ T xcontract_lanes(const T (&row)[n], T v, int wl, int nuo) {
+  T s = T(0);
+  if constexpr (n == 2 || n == 4) {
+    s += row[0] * dpp_bcast<xblock_dpp<0>()>(v);
+    s += row[1] * dpp_bcast<xblock_dpp<1>()>(v);
+    if constexpr (n == 4) {
+      s += row[2] * dpp_bcast<xblock_dpp<2>()>(v);
+      s += row[3] * dpp_bcast<xblock_dpp<3>()>(v);
+    }
+  } else {
+#pragma unroll
+    for (int nu = 0; nu < n; ++nu) s += row[nu] * __shfl(v, wl - nuo + nu, 64);
+  }
+  return s;
 }
 
 // Dirichlet smoothers' z-face traces in registers (patches of one wave):
@@ -1024,6 +1100,79 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
     line_sipg<T, false>(t, xl, sd, b, n0x, nEx);
     store_line(A, base, stride, a);
     store_line(B, base, stride, b);
+  } else if (RFA && active) {
+    static_assert(!RFA || kXShfl, "x-blocks within a wave");
+    // register face data (operator, patches of one wave): every global load
+    // first, as in k_apply_rf -- this lane's node column of each neighbour
+    // face block, the x-line and its x-neighbours' rows -- then the per-node
+    // face couplings, contracted with M_x across the lanes of the x-block
+    const int px = lane % E, q = lane / E, nuo = px % n;
+    const int wl = threadIdx.x & 63;
+    const int cx = P.lo[0] + px / n;
+    const bool ybl = (P.lo[1] == 0), ybr = (P.lo[1] + 1 == N - 1);
+    const bool zbl = (P.lo[2] == 0), zbr = (P.lo[2] + 1 == N - 1);
+    T fy0[n], fy1[n], fz0[n], fz1[n];
+    {
+      const int cz = P.lo[2] + q / n;
+      const long long o = (long long)(n * n) * (q % n) + nuo;
+      const T* c0 = x + cell_index(N, cx, ybl ? P.lo[1] : P.lo[1] - 1, cz) * NC + o;
+      const T* c1 = x + cell_index(N, cx, ybr ? P.lo[1] + 1 : P.lo[1] + 2, cz) * NC + o;
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        fy0[j] = c0[j * n];
+        fy1[j] = c1[j * n];
+      }
+    }
+    {
+      const int cy = P.lo[1] + q / n;
+      const long long o = (long long)n * (q % n) + nuo;
+      const T* c0 = x + cell_index(N, cx, cy, zbl ? P.lo[2] : P.lo[2] - 1) * NC + o;
+      const T* c1 = x + cell_index(N, cx, cy, zbr ? P.lo[2] + 1 : P.lo[2] + 2) * NC + o;
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        fz0[j] = c0[j * n * n];
+        fz1[j] = c1[j * n * n];
+      }
+    }
+    const int py = lane % E, pz = lane / E;
+    const long long row0 = xrow_offset(N, P, py, pz);
+    read_xline<T>(x, row0, xl);
+    const bool xbl = (P.lo[0] == 0), xbr = (P.lo[0] + 1 == N - 1);
+    T rl[n], rr[n];
+    {
+      const T* r0 = x + (xbl ? row0 : row0 - NC);
+      const T* r1 = x + (xbr ? row0 : row0 + 2 * NC);
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        rl[j] = r0[j];
+        rr[j] = r1[j];
+      }
+    }
+    T rowx[n];
+    mass_row<T>(nuo, rowx);
+    mass_row<T>(q % n, rowz);
+    const T sg = t->sigma;
+    T nya0, nyb0, nya1, nyb1, nza0, nzb0, nza1, nzb1;
+    face_node<T, 0>(sg, fy0, nya0, nyb0);
+    face_node<T, 1>(sg, fy1, nya1, nyb1);
+    face_node<T, 0>(sg, fz0, nza0, nzb0);
+    face_node<T, 1>(sg, fz1, nza1, nzb1);
+    const Sides<T> sd = xsides_rows<T>(sg, xbl, xbr, rl, rr);
+    int base, stride;
+    line_geom(0, lane, base, stride);
+    Line<T> a, b;
+    line_mass<T>(t, xl, a, n0x, nEx);
+    line_sipg<T, false>(t, xl, sd, b, n0x, nEx);
+    store_line(A, base, stride, a);
+    store_line(B, base, stride, b);
+    const T sya0 = xcontract_lanes<T>(rowx, nya0, wl, nuo), syb0 = xcontract_lanes<T>(rowx, nyb0, wl, nuo);
+    const T sya1 = xcontract_lanes<T>(rowx, nya1, wl, nuo), syb1 = xcontract_lanes<T>(rowx, nyb1, wl, nuo);
+    const T sza0 = xcontract_lanes<T>(rowx, nza0, wl, nuo), szb0 = xcontract_lanes<T>(rowx, nzb0, wl, nuo);
+    const T sza1 = xcontract_lanes<T>(rowx, nza1, wl, nuo), szb1 = xcontract_lanes<T>(rowx, nzb1, wl, nuo);
+    if (!ybl) { ya0 = sya0; yb0 = syb0; }
+    if (!ybr) { ya1 = sya1; yb1 = syb1; }
+    if (!zbl) { za0 = sza0; zb0 = szb0; }
+    if (!zbr) { za1 = sza1; zb1 = szb1; }
   } else if (active) {
     if constexpr (MODE != 0) ysd_global = yline_sides_global<T, MODE>(t, x, N, P, lane % E, lane / E);
     if constexpr (RFZ) {
@@ -1106,13 +1255,11 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
         } else if constexpr (RFZ) {
           sd = rfz_sides<T, MODE == 1>(N, P, i, wz0, wz1);
         } else if constexpr (RFA) {
-          T rowy[n];
-          mass_row<T>(py % n, rowy);
           const int wl = threadIdx.x & 63;
-          const T zaL = ycontract_lanes<T>(rowy, za0, wl, py % n);
-          const T zbL = ycontract_lanes<T>(rowy, zb0, wl, py % n);
-          const T zaR = ycontract_lanes<T>(rowy, za1, wl, py % n);
-          const T zbR = ycontract_lanes<T>(rowy, zb1, wl, py % n);
+          const T zaL = ycontract_lanes<T>(rowz, za0, wl, py % n);
+          const T zbL = ycontract_lanes<T>(rowz, zb0, wl, py % n);
+          const T zaR = ycontract_lanes<T>(rowz, za1, wl, py % n);
+          const T zbR = ycontract_lanes<T>(rowz, zb1, wl, py % n);
           sd.bl = (P.lo[2] == 0);
           sd.br = (P.lo[2] + 1 == N - 1);
           sd.aL = sd.bl ? T(0) : zaL;
@@ -1257,8 +1404,13 @@ k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
   const bool zbl = (P.lo[2] == 0), zbr = (P.lo[2] + 1 == N - 1);
   T ya0 = T(0), yb0 = T(0), ya1 = T(0), yb1 = T(0);
   T za0 = T(0), zb0 = T(0), za1 = T(0), zb1 = T(0);
+  // per-node face couplings of this lane's node nuo of its x-block
+  T nya0 = T(0), nyb0 = T(0), nya1 = T(0), nyb1 = T(0);
+  T nza0 = T(0), nzb0 = T(0), nza1 = T(0), nzb1 = T(0);
+  const int nuo = px % n;
   Line<T> xl;
-  if (active) {
+  if (!kXShfl && active) {
+    // x-blocks straddle waves: each lane reads whole face blocks
     const int cx = P.lo[0] + px / n;
     {
       const int cz = P.lo[2] + q / n;
@@ -1272,14 +1424,6 @@ k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
       if (!zbl) face_pair<T, 0>(t, xr + cell_index(N, cx, cy, P.lo[2] - 1) * NC + o, n * n, rowx, za0, zb0);
       if (!zbr) face_pair<T, 1>(t, xr + cell_index(N, cx, cy, P.lo[2] + 2) * NC + o, n * n, rowx, za1, zb1);
     }
-    if constexpr (!kZShfl) {  // x-contracted z-face values for the y-contraction
-      T* wz = B + TS;
-      wz[0 * NF + lane] = za0;
-      wz[1 * NF + lane] = zb0;
-      wz[2 * NF + lane] = za1;
-      wz[3 * NF + lane] = zb1;
-    }
-    // X0: a = M_x x -> A, b = L_x x -> B
     const int py = lane % E, pz = lane / E;
     const long long row0 = xrow_offset(N, P, py, pz);
     read_xline<T>(xr, row0, xl);
@@ -1291,6 +1435,84 @@ k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
     line_sipg<T, false>(t, xl, sd, b);
     store_line(A, base, stride, a);
     store_line(B, base, stride, b);
+  } else if (kXShfl && active) {
+    // Every global load first (one memory round trip): this lane's node
+    // column of each neighbour face block (n values along the normal), the
+    // x-line and the rows of its x-neighbours; missing neighbours read the
+    // patch's own cells, whose values go unused.
+    const int cx = P.lo[0] + px / n;
+    T fy0[n], fy1[n], fz0[n], fz1[n];
+    {
+      const int cz = P.lo[2] + q / n;
+      const long long o = (long long)(n * n) * (q % n) + nuo;
+      const T* c0 = xr + cell_index(N, cx, ybl ? P.lo[1] : P.lo[1] - 1, cz) * NC + o;
+      const T* c1 = xr + cell_index(N, cx, ybr ? P.lo[1] + 1 : P.lo[1] + 2, cz) * NC + o;
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        fy0[j] = c0[j * n];
+        fy1[j] = c1[j * n];
+      }
+    }
+    {
+      const int cy = P.lo[1] + q / n;
+      const long long o = (long long)n * (q % n) + nuo;
+      const T* c0 = xr + cell_index(N, cx, cy, zbl ? P.lo[2] : P.lo[2] - 1) * NC + o;
+      const T* c1 = xr + cell_index(N, cx, cy, zbr ? P.lo[2] + 1 : P.lo[2] + 2) * NC + o;
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        fz0[j] = c0[j * n * n];
+        fz1[j] = c1[j * n * n];
+      }
+    }
+    const int py = lane % E, pz = lane / E;
+    const long long row0 = xrow_offset(N, P, py, pz);
+    read_xline<T>(xr, row0, xl);
+    const bool xbl = (P.lo[0] == 0), xbr = (P.lo[0] + 1 == N - 1);
+    T rl[n], rr[n];
+    {
+      const T* r0 = xr + (xbl ? row0 : row0 - NC);
+      const T* r1 = xr + (xbr ? row0 : row0 + 2 * NC);
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        rl[j] = r0[j];
+        rr[j] = r1[j];
+      }
+    }
+    const T sg = t->sigma;
+    face_node<T, 0>(sg, fy0, nya0, nyb0);
+    face_node<T, 1>(sg, fy1, nya1, nyb1);
+    face_node<T, 0>(sg, fz0, nza0, nzb0);
+    face_node<T, 1>(sg, fz1, nza1, nzb1);
+    // X0: a = M_x x -> A, b = L_x x -> B
+    const Sides<T> sd = xsides_rows<T>(sg, xbl, xbr, rl, rr);
+    int base, stride;
+    line_geom(0, lane, base, stride);
+    Line<T> a, b;
+    line_mass<T>(t, xl, a);
+    line_sipg<T, false>(t, xl, sd, b);
+    store_line(A, base, stride, a);
+    store_line(B, base, stride, b);
+  }
+  // face couplings contracted with M_x across the lanes of each x-block
+  // (all lanes of a patch take part)
+  if constexpr (kXShfl) {
+    const T sya0 = xcontract_lanes<T>(rowx, nya0, wl, nuo), syb0 = xcontract_lanes<T>(rowx, nyb0, wl, nuo);
+    const T sya1 = xcontract_lanes<T>(rowx, nya1, wl, nuo), syb1 = xcontract_lanes<T>(rowx, nyb1, wl, nuo);
+    const T sza0 = xcontract_lanes<T>(rowx, nza0, wl, nuo), szb0 = xcontract_lanes<T>(rowx, nzb0, wl, nuo);
+    const T sza1 = xcontract_lanes<T>(rowx, nza1, wl, nuo), szb1 = xcontract_lanes<T>(rowx, nzb1, wl, nuo);
+    if (!ybl) { ya0 = sya0; yb0 = syb0; }
+    if (!ybr) { ya1 = sya1; yb1 = syb1; }
+    if (!zbl) { za0 = sza0; zb0 = szb0; }
+    if (!zbr) { za1 = sza1; zb1 = szb1; }
+  }
+  if constexpr (!kZShfl) {  // x-contracted z-face values for the y-contraction
+    if (active) {
+      T* wz = B + TS;
+      wz[0 * NF + lane] = za0;
+      wz[1 * NF + lane] = zb0;
+      wz[2 * NF + lane] = za1;
+      wz[3 * NF + lane] = zb1;
+    }
   }
   __syncthreads();
   // Y: c = M_y b + L_y a -> B, d = M_y a -> A
