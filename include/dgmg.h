@@ -123,10 +123,12 @@ dgmg_status dgmg_use_graphs(dgmg_ctx* ctx, int enable);
  * has at most 4096 DoFs, dgmg_setup_levels applies that launch to the level's
  * unit vectors and keeps the resulting nd x nd matrix (context precision; 134
  * MB for nd = 4096 in FP64) together with 8 x 16 x nd partial sums; a
- * V-cycle for at most 16 right-hand sides then applies it as one
- * matrix-vector product (the matrix read once per 8 right-hand sides), scaled
- * by kappa_setup / kappa; more right-hand sides keep the launch, which runs
- * them side by side.  Same linear map as the launch, other rounding order.  If the matrix cannot be allocated the launch stays in
+ * V-cycle for at most 16 right-hand sides then applies it as one product
+ * with the matrix, scaled by kappa_setup / kappa (one right-hand side: a
+ * matrix-vector product on the vector units; 2..16: matrix-core tiles, the
+ * matrix read once for all of them); more right-hand sides keep the launch,
+ * which runs them side by side.  Same linear map as the launch, other
+ * rounding order.  If the matrix cannot be allocated the launch stays in
  * use.  enable = 0 switches back to the launch, 1 (default) to the matrix;
  * drops the captured graphs.  dgmg_dense_bottom_level returns m, or -1 when
  * no matrix was built. */

@@ -471,9 +471,9 @@ dgmg_status ensure_levels(dgmg_ctx* c, int upto) {
   } while (0)
 
 constexpr int kDenseMaxNd = 4096;  // largest bottom operator kept dense (134 MB in FP64)
-// most right-hand sides per dense application: the matrix is read once per
-// kDenseRhs of them, while the bottom launch runs all of them side by side
-// (one workgroup each) in about the time of one
+// most right-hand sides per dense application (2..16 go through matrix-core
+// tiles that read the matrix once); beyond that the bottom launch, which runs
+// all of them side by side (one workgroup each) in about the time of one
 constexpr int kDenseMaxRhs = 16;
 
 template <typename T>

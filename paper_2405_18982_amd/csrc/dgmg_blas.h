@@ -65,8 +65,9 @@ hipError_t blas_sub(const double* a, const double* b, double* y, long long n, hi
 // Dense operator of the V-cycle's bottom levels: y_r = sc * sum_j X[j][.]
 // b_r[j] for r < nrhs, X row-major nd x nd (row j = the operator's column j),
 // b and y [nrhs][nd]; deterministic (fixed chunks summed in order, in T).
-// part: kDenseChunks * nrhs * nd values of T.  X is read once per
-// kDenseRhs right-hand sides.
+// part: kDenseChunks * nrhs * nd values of T.  One right-hand side (and
+// more than 16, in groups of kDenseRhs): vector units; 2..16: matrix cores,
+// X read once.
 constexpr int kDenseChunks = 8;
 constexpr int kDenseRhs = 8;
 template <typename T>

@@ -288,6 +288,105 @@ k_dense_part(const T* __restrict__ X, int nd, const T* __restrict__ b, int nrhs,
   }
 }
 
+// Matrix-core form of the first stage for 2..16 right-hand sides: the
+// product (right-hand sides x matrix) in 16x16x4 MFMA steps, A = the 16
+// right-hand sides' values at 4 consecutive j (zero past nrhs), B = 4 rows j
+// of 16 matrix columns, so the matrix is read once for all right-hand sides.
+// Block (64 columns i, chunk c) has one wave per j sub-chunk of chunk c, each
+// accumulating four 16x16 tiles (right-hand side x column); the waves' tiles
+// are added in wave order through LDS (two rounds of four waves) into
+// part[c][r][i].  Lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16) and
+// receives D(row, l % 16) in element v < 4 with row = l / 16 + 4 v for the
+// FP64 instruction and 4 (l / 16) + v for the FP32 one (checked on gfx950).
+typedef double dense_f64x4 __attribute__((ext_vector_type(4)));
+typedef float dense_f32x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+  using V = dense_f64x4;
+  static __device__ __forceinline__ V step(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ constexpr int row(int kq, int v) { return kq + 4 * v; }
+};
+template <>
+struct MfmaAcc<float> {
+  using V = dense_f32x4;
+  static __device__ __forceinline__ V step(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ constexpr int row(int kq, int v) { return 4 * kq + v; }
+};
+constexpr int kDenseSteps = 4;  // MFMA steps (4 j each) whose loads are issued together
+template <typename T>
+__global__ void __launch_bounds__(64 * kDenseWaves)
+k_dense_mfma(const T* __restrict__ X, int nd, const T* __restrict__ b, int nrhs, T* __restrict__ part) {
+  using V = typename MfmaAcc<T>::V;
+  __shared__ T red[kDenseWaves / 2][16][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int col = lane & 15, kq = lane >> 4;
+  int ch = (nd + kDenseChunks * kDenseWaves - 1) / (kDenseChunks * kDenseWaves);
+  ch = (ch + 3) & ~3;
+  const int j0 = (blockIdx.y * kDenseWaves + w) * ch;
+  const int j1 = (j0 + ch < nd) ? j0 + ch : nd;
+  const int c0 = blockIdx.x * 64;
+  const bool rok = col < nrhs;
+  const T* __restrict__ bp = b + (long long)(rok ? col : 0) * nd;
+  bool cok[4];
+  const T* __restrict__ xp[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int i = c0 + 16 * t + col;
+    cok[t] = i < nd;
+    xp[t] = X + (cok[t] ? i : 0);
+  }
+  V acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = V{};
+  for (int jj = j0; jj < j1; jj += 4 * kDenseSteps) {
+    T av[kDenseSteps], bv[kDenseSteps][4];
+#pragma unroll
+    for (int u = 0; u < kDenseSteps; ++u) {
+      const int j = jj + 4 * u + kq;
+      const bool jok = j < j1;
+      av[u] = (jok && rok) ? bp[j] : T(0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bv[u][t] = (jok && cok[t]) ? xp[t][(long long)j * nd] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kDenseSteps; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = MfmaAcc<T>::step(av[u], bv[u][t], acc[t]);
+  }
+  // waves 0..3, then 4..7, added in wave order
+  const int tr = threadIdx.x >> 6, tc = threadIdx.x & 63;  // this thread's outputs: rows tr, tr + 8
+  T sum[2] = {T(0), T(0)};
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    if (w / 4 == half)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[w % 4][MfmaAcc<T>::row(kq, v)][16 * t + col] = acc[t][v];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T x = red[v][tr + 8 * e][tc];
+        sum[e] = (half == 0 && v == 0) ? x : sum[e] + x;
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int r = tr + 8 * e, i = c0 + tc;
+    if (r < nrhs && i < nd) part[((long long)blockIdx.y * nrhs + r) * nd + i] = sum[e];
+  }
+}
+
 template <typename T, int NR>
 void launch_dense_part(const T* X, int nd, const T* b, int nrhs, int r0, T* part, hipStream_t s) {
   const dim3 g((nd + 63) / 64, kDenseChunks);
@@ -423,6 +522,10 @@ hipError_t blas_zero_f32(float* a, long long n, hipStream_t s) {
 template <typename T>
 hipError_t dense_apply(const T* X, int nd, const T* b, T* y, int nrhs, T sc, T* part, hipStream_t s) {
   if (nd <= 0 || nrhs <= 0) return hipErrorInvalidValue;
+  if (nrhs > 1 && nrhs <= 16) {
+    const dim3 g((nd + 63) / 64, kDenseChunks);
+    hipLaunchKernelGGL((k_dense_mfma<T>), g, dim3(64 * kDenseWaves), 0, s, X, nd, b, nrhs, part);
+  } else
   for (int r0 = 0; r0 < nrhs; r0 += kDenseRhs) {
     switch (nrhs - r0 < kDenseRhs ? nrhs - r0 : kDenseRhs) {
       case 1: launch_dense_part<T, 1>(X, nd, b, nrhs, r0, part, s); break;
