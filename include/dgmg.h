@@ -120,9 +120,10 @@ dgmg_status dgmg_use_graphs(dgmg_ctx* ctx, int enable);
  * m, with m = 1 in 3-D and m = 2 in 2-D) map the level-m right-hand side
  * linearly to the level-m correction.  Where those levels run as one fused
  * launch (not for the Full smoother), level m lies below the finest level and
- * has at most 4096 DoFs, dgmg_setup_levels applies that launch to the level's
- * unit vectors and keeps the resulting nd x nd matrix (context precision; 134
- * MB for nd = 4096 in FP64) together with 8 x 16 x nd partial sums; a
+ * has at most 8192 DoFs, dgmg_setup_levels applies that launch to the level's
+ * unit vectors and keeps the resulting nd x nd matrix (context precision;
+ * 134 MB for 3-D Q3, nd = 4096, in FP64; 256 MB for 3-D Q4, nd = 8000, in
+ * FP32) together with 8 x 16 x nd partial sums; a
  * V-cycle for at most 16 right-hand sides then applies it as one product
  * with the matrix, scaled by kappa_setup / kappa (one right-hand side: a
  * matrix-vector product on the vector units; 2..16: matrix-core tiles, the

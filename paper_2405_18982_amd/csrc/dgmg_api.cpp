@@ -470,7 +470,7 @@ dgmg_status ensure_levels(dgmg_ctx* c, int upto) {
     if (s_ != DGMG_OK) return s_;          \
   } while (0)
 
-constexpr int kDenseMaxNd = 4096;  // largest bottom operator kept dense (134 MB in FP64)
+constexpr int kDenseMaxNd = 8192;  // largest bottom operator kept dense (537 MB in FP64)
 // most right-hand sides per dense application (2..16 go through matrix-core
 // tiles that read the matrix once); beyond that the bottom launch, which runs
 // all of them side by side (one workgroup each) in about the time of one

@@ -749,13 +749,38 @@ __device__ __forceinline__ Sides<T> yside_finish(const YSideRaw<T>& y, int N, co
   }
   return sd;
 }
+// The same in one step (loads only the sides that exist, fewer live values).
 template <typename T, int MODE>
 __device__ __forceinline__ Sides<T> yline_sides_global(const Tab<K, T>* __restrict__ t,
                                                        const T* __restrict__ x, int N,
                                                        const PatchPos& P, int px, int pz) {
-  YSideRaw<T> y;
-  yside_load<T, MODE>(x, N, P, px, pz, y);
-  return yside_finish<T, MODE>(y, N, P);
+  Sides<T> sd;
+  sd.bl = (P.lo[1] == 0);
+  sd.br = (P.lo[1] + 1 == N - 1);
+  sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+  sd.lit = (MODE == 2);
+  if (MODE == 2) return sd;
+  const int cx = P.lo[0] + px / n;
+  const int cz = (D == 3) ? P.lo[2] + pz / n : 0;
+  const int az = (D == 3) ? pz % n : 0;
+  const T half = T(0.5);
+  T row[n];
+  if (!sd.bl || !sd.br) mass_row<T>(px % n, row);
+  if (!sd.bl) {
+    const T* r = x + cell_index(N, cx, P.lo[1] - 1, cz) * NC + K * n + az * n * n;
+    T s = T(0);
+#pragma unroll
+    for (int nu = 0; nu < n; ++nu) s += row[nu] * r[nu];
+    sd.bL = -half * s;
+  }
+  if (!sd.br) {
+    const T* r = x + cell_index(N, cx, P.lo[1] + 2, cz) * NC + az * n * n;
+    T s = T(0);
+#pragma unroll
+    for (int nu = 0; nu < n; ++nu) s += row[nu] * r[nu];
+    sd.bR = half * s;
+  }
+  return sd;
 }
 
 // In the y-phase the z-face arrays are contracted along x in place (lines at
@@ -2117,52 +2142,77 @@ __device__ __forceinline__ void smooth_split_body(const Tab<K, T>* __restrict__ 
     }
     __syncthreads();
   } else {
-    // Every global load of the first phases is issued here, before any of
-    // the values is used (one memory round trip instead of one per helper):
-    // the y-neighbour traces with their mass row, this lane's z-face trace,
-    // the x-line with its x-neighbour traces and the mass row of the z-sides.
+    // Q3: every global load of the first phases is issued here, before any
+    // of the values is used (one memory round trip instead of one per
+    // helper): the y-neighbour traces with their mass row, this lane's z-face
+    // trace, the x-line with its x-neighbour traces and the mass row of the
+    // z-sides.  For 16-point lines the registers this holds would cost a
+    // wave per SIMD, so there the helpers load one after the other.
     static_assert(TPP == NF, "one z-face trace per lane of the two waves");
-    YSideRaw<T> yraw;
-    T ztr = T(0), xtl = T(0), xtr = T(0);
+    constexpr bool HOIST = (n <= 4);
+    Sides<T> ysd{}, sd{};
     T zrow[n];
     Line<T> xl;
-    const int zf = lane, zside = H;  // this lane's z-face entry (face node, side)
-    const int znb = (zside == 0) ? P.lo[2] - 1 : P.lo[2] + 2;
-    const bool zhas = MODE == 1 && znb >= 0 && znb < g.N;
     const int py = lane % E, pz = lane / E;
     const long long row0 = xrow_offset(g.N, P, py, pz);
-    const bool xbl = (P.lo[0] == 0), xbr = (P.lo[0] + 1 == g.N - 1);
-    if (active) {
-      yside_load<T, OPM>(xr, g.N, P, lane % E, lane / E, yraw);
-      if (MODE == 1) {
-        const int a = zf % E, bb = zf / E;
-        const long long base = cell_index(g.N, P.lo[0] + a / n, P.lo[1] + bb / n, zhas ? znb : P.lo[2]) * NC +
-                               a % n + n * (bb % n);
-        ztr = xr[base + (long long)((zside == 0) ? K : 0) * n * n];
+    if constexpr (HOIST) {
+      YSideRaw<T> yraw;
+      T ztr = T(0), xtl = T(0), xtr = T(0);
+      const int zf = lane, zside = H;  // this lane's z-face entry (face node, side)
+      const int znb = (zside == 0) ? P.lo[2] - 1 : P.lo[2] + 2;
+      const bool zhas = MODE == 1 && znb >= 0 && znb < g.N;
+      const bool xbl = (P.lo[0] == 0), xbr = (P.lo[0] + 1 == g.N - 1);
+      if (active) {
+        yside_load<T, OPM>(xr, g.N, P, lane % E, lane / E, yraw);
+        if (MODE == 1) {
+          const int a = zf % E, bb = zf / E;
+          const long long base = cell_index(g.N, P.lo[0] + a / n, P.lo[1] + bb / n, zhas ? znb : P.lo[2]) * NC +
+                                 a % n + n * (bb % n);
+          ztr = xr[base + (long long)((zside == 0) ? K : 0) * n * n];
+        }
+        read_xline<T>(xr, row0, xl);
+        if (OPM != 2) {
+          xtl = xr[xbl ? row0 : row0 - NC + K];
+          xtr = xr[xbr ? row0 : row0 + 2 * NC];
+        }
+        mass_row<T>((lane / E) % n, zrow);
+        ysd = yside_finish<T, OPM>(yraw, g.N, P);
+        // z-face traces, spread over both waves (the register form of the
+        // one-wave kernel measured slower here: both waves would repeat it)
+        ext[zside * NF + zf] = zhas ? ((zside == 0) ? -T(0.5) * ztr : T(0.5) * ztr) : T(0);
+        // x-sides as xline_sides forms them for the smoother's residual
+        sd.bl = xbl;
+        sd.br = xbr;
+        sd.aL = sd.bL = sd.aR = sd.bR = T(0);
+        sd.lit = (OPM == 2);
+        if (OPM != 2) {
+          if (!sd.bl) sd.bL = -T(0.5) * xtl;
+          if (!sd.br) sd.bR = T(0.5) * xtr;
+        }
       }
-      read_xline<T>(xr, row0, xl);
-      if (OPM != 2) {
-        xtl = xr[xbl ? row0 : row0 - NC + K];
-        xtr = xr[xbr ? row0 : row0 + 2 * NC];
+    } else {
+      if (active) ysd = yline_sides_global<T, OPM>(t, xr, g.N, P, lane % E, lane / E);
+      if (active) {
+        for (int i = lane + H * TPP; i < 2 * NF; i += 2 * TPP) {
+          const int f = i % NF;
+          const int side = i / NF;
+          const int nb = (side == 0) ? P.lo[2] - 1 : P.lo[2] + 2;
+          T beta = T(0);
+          if (MODE == 1 && nb >= 0 && nb < g.N) {
+            const int a = f % E, bb = f / E;
+            const long long base = cell_index(g.N, P.lo[0] + a / n, P.lo[1] + bb / n, nb) * NC + a % n +
+                                   n * (bb % n);
+            const T tr = xr[base + (long long)((side == 0) ? K : 0) * n * n];
+            beta = (side == 0) ? -T(0.5) * tr : T(0.5) * tr;
+          }
+          ext[side * NF + f] = beta;
+        }
+        read_xline<T>(xr, row0, xl);
+        sd = xline_sides<T, OPM>(t, xr, g.N, P, row0);
       }
-      mass_row<T>((lane / E) % n, zrow);
     }
-    const Sides<T> ysd = active ? yside_finish<T, OPM>(yraw, g.N, P) : Sides<T>{};
     // X0: a = M_x x, b = L_x x on this half -> A, B
     if (active) {
-      // z-face traces, spread over both waves (the register form of the
-      // one-wave kernel measured slower here: both waves would repeat it)
-      ext[zside * NF + zf] = zhas ? ((zside == 0) ? -T(0.5) * ztr : T(0.5) * ztr) : T(0);
-      // x-sides as xline_sides forms them for the smoother's residual
-      Sides<T> sd;
-      sd.bl = xbl;
-      sd.br = xbr;
-      sd.aL = sd.bL = sd.aR = sd.bR = T(0);
-      sd.lit = (OPM == 2);
-      if (OPM != 2) {
-        if (!sd.bl) sd.bL = -T(0.5) * xtl;
-        if (!sd.br) sd.bR = T(0.5) * xtr;
-      }
 #pragma unroll
       for (int j = 0; j < n; ++j) xh.v[j] = xl.v[H * n + j];
       int base, stride;
@@ -2205,7 +2255,9 @@ __device__ __forceinline__ void smooth_split_body(const Tab<K, T>* __restrict__ 
       Line<T> cl, dl;
       load_line(B, base, stride, cl);
       load_line(A, base, stride, dl);
-      Sides<T> sd = zline_sides_row<T>(zrow, ext, g.N, P, px, py);
+      Sides<T> sd;
+      if constexpr (HOIST) sd = zline_sides_row<T>(zrow, ext, g.N, P, px, py);
+      else sd = zline_sides<T, 1>(t, ext, g.N, P, px, py);
       sd.lit = (OPM == 2);
       Half<T> y;
       half_mass<T, H>(cl, y, endz);
