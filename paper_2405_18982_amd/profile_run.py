@@ -3,8 +3,9 @@
 `run` drives the finest-level kernels of one workload (autotuned shapes): a
 32 MiB torch copy (the calibration kernel that scales the HBM counters to
 bytes), then `reps` applications of the operator and `reps` smoothing steps
-in the chosen precision, on x, b ~ U[-1,1] with the workload's right-hand
-side count.  Run it under rocprofv3, e.g.
+in the chosen precision (with `--vcycle`: `reps` V-cycles), on x, b ~ U[-1,1]
+with the workload's right-hand side count (or `--nrhs`).  Run it under
+rocprofv3, e.g.
 
     rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_LDS -d OUT -o run --output-format csv -- \\
         python -m paper_2405_18982_amd.profile_run run --workload poisson3d_q3_32c --prec 64
@@ -30,11 +31,11 @@ from . import inputs
 CAL_BYTES = 32 * 1024 * 1024
 
 
-def run(workload, prec, reps, smooth_only=False):
+def run(workload, prec, reps, smooth_only=False, nrhs=None, vcycle=False):
     import torch
     from . import dgmg
     w = inputs.WORKLOADS[workload]
-    nr = w["nrhs"]
+    nr = w["nrhs"] if nrhs is None else nrhs
     prob = dgmg.Problem(w["dim"], w["k"], w["L"], precision=prec, nrhs_max=nr)
     print(prob.autotune(nrhs=nr), flush=True)
     src = torch.ones(CAL_BYTES // 8, dtype=torch.float64, device="cuda")
@@ -49,11 +50,15 @@ def run(workload, prec, reps, smooth_only=False):
     b = torch.from_numpy(inputs.uniform(8, shape)).to(device="cuda", dtype=dt)
     y = torch.empty_like(x)
     for _ in range(reps):
+        if vcycle:
+            prob.vcycle(b, out=y)
+            continue
         if not smooth_only:
             prob.apply(x, out=y)
         prob.smooth(x, b)
     torch.cuda.synchronize()
-    print(f"profile_run: {workload} fp{prec} nrhs={nr} reps={reps} done", flush=True)
+    what = "V-cycles" if vcycle else "reps"
+    print(f"profile_run: {workload} fp{prec} nrhs={nr} {what}={reps} done", flush=True)
     prob.close()
 
 
@@ -122,6 +127,8 @@ def main():
     r.add_argument("--prec", type=int, default=64, choices=(64, 32))
     r.add_argument("--reps", type=int, default=4)
     r.add_argument("--smooth-only", action="store_true")
+    r.add_argument("--nrhs", type=int, default=None, help="right-hand sides (default: the workload's)")
+    r.add_argument("--vcycle", action="store_true", help="run V-cycles instead of apply + smoothing step")
     s = sub.add_parser("summarize")
     s.add_argument("csv")
     s.add_argument("--match", default=None)
@@ -131,7 +138,7 @@ def main():
     t.add_argument("--top", type=int, default=40)
     a = ap.parse_args()
     if a.cmd == "run":
-        run(a.workload, a.prec, a.reps, a.smooth_only)
+        run(a.workload, a.prec, a.reps, a.smooth_only, a.nrhs, a.vcycle)
     elif a.cmd == "summarize":
         summarize(a.csv, a.match)
     else:
