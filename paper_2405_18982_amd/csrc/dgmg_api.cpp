@@ -1184,7 +1184,7 @@ DGMG_API dgmg_status dgmg_gmres_solve(dgmg_ctx* c, const double* b, double* x, d
   hist[0] = 1.0;
   RET(zero_vec<double>(c, x, n));
   if (beta == 0) return DGMG_OK;
-  HIPCHK(c, dgmg::blas_normalise(c->gm_V, b, nn, n, s));
+  HIPCHK(c, dgmg::blas_normalise(c->gm_V, c->r, b, nn, n, s));
   // Hessenberg matrix (column-major, (maxit + 1) x maxit), Givens rotations,
   // and the rotated right-hand side g
   std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0);
@@ -1204,14 +1204,13 @@ DGMG_API dgmg_status dgmg_gmres_solve(dgmg_ctx* c, const double* b, double* x, d
       RET(ensure_gmres(c, want, j + 1, j));
       bind();
     }
-    double* vj = c->gm_V + (long long)j * n;
     double* zj = c->gm_Z + (long long)j * n;
     // z_j = V(v_j) through the CG workspace (graph replay), w = A z_j in q.
-    // The captured V-cycle reads r and writes z, hence the two vector copies;
-    // they cost less than running the ~80 launches of a V-cycle on v_j and
-    // z_j directly (on a stream a launch costs ~0.7 us more than in a graph;
-    // a 3-D Q3 32^3 vector copies in ~7 us).
-    HIPCHK(c, hipMemcpyAsync(c->r, vj, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    // The captured V-cycle reads r and writes z: v_j was written into r as
+    // well when it was normalised, z_j is copied out of z (cheaper than
+    // running the ~80 launches of a V-cycle on z_j directly: on a stream a
+    // launch costs ~0.7 us more than in a graph; a 3-D Q3 32^3 vector copies
+    // in ~7 us).
     RET(precondition_cg(c, 1));
     HIPCHK(c, hipMemcpyAsync(zj, c->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     RET(op_apply<double>(c, c->L, zj, c->q, 1));
@@ -1231,7 +1230,7 @@ DGMG_API dgmg_status dgmg_gmres_solve(dgmg_ctx* c, const double* b, double* x, d
     if (!std::isfinite(w2) || !(w2 >= 0)) return fail(c, DGMG_ERR_BREAKDOWN, "GMRES: non-finite Arnoldi scalar");
     Hj[j + 1] = std::sqrt(w2);
     if (w2 > 0 && j + 1 < maxit)
-      HIPCHK(c, dgmg::blas_normalise(c->gm_V + (long long)(j + 1) * n, c->q, nn, n, s));
+      HIPCHK(c, dgmg::blas_normalise(c->gm_V + (long long)(j + 1) * n, c->r, c->q, nn, n, s));
     // apply the previous rotations to the new column, then a new one
     for (int i = 0; i < j; ++i) {
       const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];

@@ -54,8 +54,9 @@ hipError_t blas_multi_dot(const double* V, const double* w, long long n, int m, 
 // w += sgn * sum_i coef[i] V_i (coef: device array of m doubles).
 hipError_t blas_multi_axpy(double* w, const double* V, const double* coef, int m, double sgn,
                            long long n, hipStream_t s);
-// v = w / sqrt(nn[0]).
-hipError_t blas_normalise(double* v, const double* w, const double* nn, long long n, hipStream_t s);
+// v = w / sqrt(nn[0]), and the same into v2 unless it is null.
+hipError_t blas_normalise(double* v, double* v2, const double* w, const double* nn, long long n,
+                          hipStream_t s);
 hipError_t blas_f64_to_f32(const double* a, float* b, long long n, hipStream_t s);
 hipError_t blas_f32_to_f64(const float* a, double* b, long long n, hipStream_t s);
 hipError_t blas_zero_f64(double* a, long long n, hipStream_t s);

@@ -211,12 +211,15 @@ k_multi_axpy(double* __restrict__ w, const double* __restrict__ V, const double*
 
 // v = w / sqrt(nn[0]) (nn > 0 is checked by the host before the basis is used)
 __global__ void __launch_bounds__(kRedThreads)
-k_normalise(double* __restrict__ v, const double* __restrict__ w, const double* __restrict__ nn,
-            long long n) {
+k_normalise(double* __restrict__ v, double* __restrict__ v2, const double* __restrict__ w,
+            const double* __restrict__ nn, long long n) {
   const double inv = 1.0 / sqrt(nn[0]);
   const long long stride = (long long)gridDim.x * kRedThreads;
-  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride)
-    v[i] = w[i] * inv;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
+    const double y = w[i] * inv;
+    v[i] = y;
+    if (v2) v2[i] = y;
+  }
 }
 
 // y = a - b  (residual r = b - A x)
@@ -448,8 +451,9 @@ hipError_t blas_multi_axpy(double* w, const double* V, const double* coef, int m
   return hipGetLastError();
 }
 
-hipError_t blas_normalise(double* v, const double* w, const double* nn, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalise, dim3(grid_for(n)), dim3(kRedThreads), 0, s, v, w, nn, n);
+hipError_t blas_normalise(double* v, double* v2, const double* w, const double* nn, long long n,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_normalise, dim3(grid_for(n)), dim3(kRedThreads), 0, s, v, v2, w, nn, n);
   return hipGetLastError();
 }
 
