@@ -114,25 +114,23 @@ dgmg_status dgmg_set_kappa(dgmg_ctx* ctx, double kappa);
  * host.  Both give bitwise identical results.  A new kappa drops the graphs. */
 dgmg_status dgmg_use_graphs(dgmg_ctx* ctx, int enable);
 
-/* The V-cycle's bottom as a dense operator.  The coarsest levels of the
- * V-cycle (Sec. 3: pre-smoothing on level m, restriction, the exact solve on
- * level 0 and, in 2-D, also on level 1, prolongation, post-smoothing on level
- * m, with m = 1 in 3-D and m = 2 in 2-D) map the level-m right-hand side
- * linearly to the level-m correction.  Where those levels run as one fused
- * launch (not for the Full smoother), level m lies below the finest level and
- * has at most 8192 DoFs, dgmg_setup_levels applies that launch to the level's
- * unit vectors and keeps the resulting nd x nd matrix (context precision;
- * 134 MB for 3-D Q3, nd = 4096, in FP64; 256 MB for 3-D Q4, nd = 8000, in
- * FP32) together with 8 x 16 x nd partial sums; a
- * V-cycle for at most 16 right-hand sides then applies it as one product
- * with the matrix, scaled by kappa_setup / kappa (one right-hand side: a
+/* The V-cycle's bottom as a dense operator.  Below a level m the V-cycle
+ * (Sec. 3: smoothing, restriction, the exact solve on level 0, prolongation,
+ * smoothing) maps the level-m right-hand side linearly to the level-m
+ * correction.  For m = the finest level below L with at most 8192 DoFs (none
+ * for L = 1; not for the Full smoother), dgmg_setup_levels runs the cycle from
+ * level m on that level's unit vectors and keeps the resulting nd x nd matrix
+ * (context precision; 134 MB for 3-D Q3, nd = 4096, in FP64; 512 MB for 3-D
+ * Q4, nd = 8000, in FP64) together with 8 x 16 x nd partial sums; a V-cycle
+ * for at most 16 right-hand sides then applies it as one product with the
+ * matrix, scaled by kappa_setup / kappa (one right-hand side: a
  * matrix-vector product on the vector units; 2..16: matrix-core tiles, the
- * matrix read once for all of them); more right-hand sides keep the launch,
- * which runs them side by side.  Same linear map as the launch, other
- * rounding order.  If the matrix cannot be allocated the launch stays in
- * use.  enable = 0 switches back to the launch, 1 (default) to the matrix;
- * drops the captured graphs.  dgmg_dense_bottom_level returns m, or -1 when
- * no matrix was built. */
+ * matrix read once for all of them); more right-hand sides keep the
+ * kernels, which run them side by side.  Same linear map as the kernels,
+ * other rounding order.  If the matrix cannot be allocated the kernels stay
+ * in use.  enable = 0 switches back to the kernels, 1 (default) to the
+ * matrix; drops the captured graphs.  dgmg_dense_bottom_level returns m, or
+ * -1 when no matrix was built. */
 dgmg_status dgmg_use_dense_bottom(dgmg_ctx* ctx, int enable);
 int dgmg_dense_bottom_level(const dgmg_ctx* ctx);
 

@@ -197,10 +197,9 @@ struct dgmg_ctx {
   // device address of the library's scratch array on this context's device
   // (dgmg_vcycle_noalloc), looked up in dgmg_setup_levels
   void* scratch = nullptr;
-  // The V-cycle's bottom levels 0..dense_lvl (those the fused bottom launch
-  // runs) as a dense operator in the V-cycle precision, built at set-up from
-  // the bottom launch applied to unit vectors (row j = the operator's column
-  // j); applied with the scale dense_kappa / kappa (the V-cycle of kappa A_1
+  // The V-cycle's bottom levels 0..dense_lvl as a dense operator in the
+  // V-cycle precision, built at set-up from the cycle from level dense_lvl
+  // applied to unit vectors (row j = the operator's column j); applied with the scale dense_kappa / kappa (the V-cycle of kappa A_1
   // is that of A_1 divided by kappa) to at most kDenseMaxRhs right-hand
   // sides.  dense_part: the application's partial sums.
   int dense_lvl = -1;
@@ -494,25 +493,29 @@ struct VBufs {
 
 // x = V(b) on level L with b, x given (may be caller or library buffers);
 // coarser levels use the vectors of `bufs`, else the library's own of
-// precision T.
+// precision T.  top >= 0: the cycle from level top instead of L (b, x on
+// that level).
 template <typename T>
-dgmg_status vcycle_T(dgmg_ctx* c, const T* bL, T* xL, int nrhs, const VBufs<T>* bufs = nullptr) {
+dgmg_status vcycle_T(dgmg_ctx* c, const T* bL, T* xL, int nrhs, const VBufs<T>* bufs = nullptr,
+                     int top = -1) {
   if (!bufs) RET(ensure_levels<T>(c, c->L - 1));
-  const int L = c->L;
+  const int L = top < 0 ? c->L : top;
   auto Bw = [&](int l) -> T* { return bufs ? bufs->b[l] : lvb<T>(c->lv[l]); };
   auto B = [&](int l) -> const T* { return l == L ? bL : Bw(l); };
   auto X = [&](int l) -> T* { return l == L ? xL : (bufs ? bufs->x[l] : lvx<T>(c->lv[l])); };
   auto Alt = [&](int l) -> T* { return bufs ? bufs->alt[l] : nullptr; };
   // levels 1 and 0 (2-D: 2, 1 and 0) in one launch (same arithmetic as the
-  // separate kernels)
+  // separate kernels), or levels 0..dense_lvl as one product with their
+  // dense operator
   const bool fuse = c->fuse_bottom && kset<T>(c).bottom && c->variant != DGMG_SMOOTH_FULL;
   const bool fuse3 = fuse && c->fuse_bottom >= 2 && kset<T>(c).bottom3 && L >= 2;
-  const int lo = fuse3 ? 3 : fuse ? 2 : 1;
+  const bool dense = c->use_dense && dense_of<T>(c) && c->dense_lvl < L && nrhs <= kDenseMaxRhs;
+  const int lo = dense ? c->dense_lvl + 1 : fuse3 ? 3 : fuse ? 2 : 1;
   for (int l = L; l >= lo; --l) {
     RET(op_smooth<T>(c, l, X(l), B(l), 0, nrhs, true, Alt(l)));
     RET(op_restrict<T>(c, l, X(l), B(l), Bw(l - 1), nrhs));
   }
-  if (fuse && c->use_dense && dense_of<T>(c) && c->dense_lvl == lo - 1 && nrhs <= kDenseMaxRhs) {
+  if (dense) {
     HIPCHK(c, dgmg::dense_apply<T>(dense_of<T>(c), c->dense_nd, B(lo - 1), X(lo - 1), nrhs,
                                    (T)(c->dense_kappa / c->kappa), (T*)c->dense_part, c->stream));
   } else if (fuse3) {
@@ -574,17 +577,17 @@ dgmg_status precondition(dgmg_ctx* c, const double* r, double* z, int nrhs) {
 }
 
 // The bottom levels of the V-cycle as a dense operator (see dgmg_ctx): the
-// fused bottom launch applied to the nd unit vectors of level m gives the
-// operator's columns.  Only where that launch is used, level m lies below the
-// finest level and nd <= kDenseMaxNd; an allocation failure leaves the
-// context without it (the bottom launch stays in use).
+// cycle from level m (the finest level below L with at most kDenseMaxNd
+// DoFs), applied to the nd unit vectors of level m, gives the operator's
+// columns.  Not for the Full smoother (its second copies of x); an
+// allocation failure leaves the context without it (the kernels stay in use).
 template <typename T>
 dgmg_status build_dense(dgmg_ctx* c) {
-  const bool fuse = c->fuse_bottom && kset<T>(c).bottom && c->variant != DGMG_SMOOTH_FULL;
-  if (!fuse) return DGMG_OK;
-  const bool fuse3 = c->fuse_bottom >= 2 && kset<T>(c).bottom3 && c->L >= 2;
-  const int m = fuse3 ? 2 : 1;
-  if (m >= c->L || c->lv[m].ndof > kDenseMaxNd) return DGMG_OK;
+  if (c->variant == DGMG_SMOOTH_FULL) return DGMG_OK;
+  int m = 0;
+  for (int l = 1; l < c->L; ++l)
+    if (c->lv[l].ndof <= kDenseMaxNd) m = l;
+  if (m == 0) return DGMG_OK;
   const int nd = (int)c->lv[m].ndof;
   hipError_t e = hipSuccess;
   std::vector<void*> tmp;
@@ -600,11 +603,10 @@ dgmg_status build_dense(dgmg_ctx* c) {
   };
   T* Xm = alloc((long long)nd * nd);
   T* Bm = alloc((long long)nd * nd);
-  T* bl[3] = {nullptr, nullptr, nullptr};
-  T* xl[3] = {nullptr, nullptr, nullptr};
+  VBufs<T> bufs;
   for (int l = 0; l < m; ++l) {
-    bl[l] = alloc(c->lv[l].ndof * nd);
-    xl[l] = alloc(c->lv[l].ndof * nd);
+    bufs.b[l] = alloc(c->lv[l].ndof * nd);
+    bufs.x[l] = alloc(c->lv[l].ndof * nd);
   }
   T* part = alloc((long long)dgmg::kDenseChunks * kDenseMaxRhs * nd);
   if (e != hipSuccess) {
@@ -612,23 +614,14 @@ dgmg_status build_dense(dgmg_ctx* c) {
     release();
     return DGMG_OK;
   }
-  const double s1 = level_scale(c, 1);
+  dgmg_status st = DGMG_OK;
   e = dgmg::unit_batch<T>(Bm, nd, 0, nd, c->stream);
-  if (e == hipSuccess && fuse3) {
-    const double s2 = level_scale(c, 2);
-    e = kset<T>(c).bottom3(tab_of<T>(c), c->variant, (T)s2, (T)(1.0 / s2), (T)s1, (T)(1.0 / s1),
-                           (T)(1.0 / level_scale(c, 0)), Xm, Bm, xl[1], bl[1], bl[0], xl[0], nd,
-                           c->lv[2].ndof, c->lv[1].ndof, c->lv[0].ndof, c->stream);
-  } else if (e == hipSuccess) {
-    const int split = (c->fuse_bottom >= 2 && kset<T>(c).bottom_split) ? 1 : 0;
-    e = kset<T>(c).bottom(tab_of<T>(c), c->variant, split, (T)s1, (T)(1.0 / s1),
-                          (T)(1.0 / level_scale(c, 0)), Xm, Bm, bl[0], xl[0], nd, c->lv[1].ndof,
-                          c->lv[0].ndof, c->stream);
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) {
+  if (e == hipSuccess) st = vcycle_T<T>(c, Bm, Xm, nd, &bufs, m);
+  if (e == hipSuccess && st == DGMG_OK) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess || st != DGMG_OK) {
     (void)hipStreamSynchronize(c->stream);
     release();
+    if (st != DGMG_OK) return st;
     return fail(c, DGMG_ERR_HIP, std::string("dense bottom set-up: ") + hipGetErrorString(e));
   }
   // keep the operator and the partial sums, free the rest
