@@ -53,3 +53,16 @@ def test_trace_durations_per_kernel_and_grid(tmp_path, capsys):
     assert abs(float(first[3]) - 10.0) < 1e-9 and abs(float(first[4]) - 30.0) < 1e-9
     assert first[6] == "256" and first[-1] == "k_a"
     assert any(ln.split()[6] == "128" and float(ln.split()[2]) == 4.0 for ln in lines)
+
+
+def test_run_options_parse():
+    """The profiler driver's run command takes the right-hand side count and
+    the V-cycle mode (parsed on the host; no GPU call is made here)."""
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-m", "paper_2405_18982_amd.profile_run", "run", "--help"],
+                         capture_output=True, text=True, cwd=root, timeout=120)
+    assert out.returncode == 0
+    assert "--nrhs" in out.stdout and "--vcycle" in out.stdout and "--smooth-only" in out.stdout
