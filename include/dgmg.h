@@ -118,7 +118,7 @@ dgmg_status dgmg_use_graphs(dgmg_ctx* ctx, int enable);
  * (Sec. 3: smoothing, restriction, the exact solve on level 0, prolongation,
  * smoothing) maps the level-m right-hand side linearly to the level-m
  * correction.  For m = the finest level below L with at most 8192 DoFs (none
- * for L = 1; not for the Full smoother), dgmg_setup_levels runs the cycle from
+ * for L = 1), dgmg_setup_levels runs the cycle from
  * level m on that level's unit vectors and keeps the resulting nd x nd matrix
  * (context precision; 134 MB for 3-D Q3, nd = 4096, in FP64; 512 MB for 3-D
  * Q4, nd = 8000, in FP64) together with 8 x 16 x nd partial sums; a V-cycle

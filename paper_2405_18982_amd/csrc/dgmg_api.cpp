@@ -579,11 +579,10 @@ dgmg_status precondition(dgmg_ctx* c, const double* r, double* z, int nrhs) {
 // The bottom levels of the V-cycle as a dense operator (see dgmg_ctx): the
 // cycle from level m (the finest level below L with at most kDenseMaxNd
 // DoFs), applied to the nd unit vectors of level m, gives the operator's
-// columns.  Not for the Full smoother (its second copies of x); an
+// columns (the Full smoother with second copies of x on levels 1..m).  An
 // allocation failure leaves the context without it (the kernels stay in use).
 template <typename T>
 dgmg_status build_dense(dgmg_ctx* c) {
-  if (c->variant == DGMG_SMOOTH_FULL) return DGMG_OK;
   int m = 0;
   for (int l = 1; l < c->L; ++l)
     if (c->lv[l].ndof <= kDenseMaxNd) m = l;
@@ -608,6 +607,8 @@ dgmg_status build_dense(dgmg_ctx* c) {
     bufs.b[l] = alloc(c->lv[l].ndof * nd);
     bufs.x[l] = alloc(c->lv[l].ndof * nd);
   }
+  if (c->variant == DGMG_SMOOTH_FULL)
+    for (int l = 1; l <= m; ++l) bufs.alt[l] = alloc(c->lv[l].ndof * nd);
   T* part = alloc((long long)dgmg::kDenseChunks * kDenseMaxRhs * nd);
   if (e != hipSuccess) {
     (void)hipGetLastError();

@@ -382,15 +382,15 @@ MODES = {0: "exact", 1: "local", 2: "full", 3: "clamped"}
     (3, 3, 2, 64, 0, 1), (3, 3, 2, 32, 1, 1), (3, 3, 2, 64, 3, 1), (3, 2, 3, 64, 0, 1),
     (3, 1, 3, 32, 0, 2), (2, 5, 3, 64, 0, 2), (2, 7, 3, 32, 3, 2), (2, 3, 4, 64, 1, 3),
     (3, 4, 2, 32, 0, 1), (3, 4, 2, 64, 0, 1), (2, 3, 2, 64, 0, 1), (2, 2, 1, 64, 0, -1),
-    (3, 3, 2, 64, 2, -1)])
+    (3, 3, 2, 64, 2, 1), (2, 4, 3, 32, 2, 2)])
 def test_dense_bottom_equals_bottom_launch(dim, k, L, precision, variant, level):
     """The V-cycle with its bottom levels (0..level: the finest level below
     L with at most 8192 DoFs) as the dense operator built at set-up equals
     the V-cycle with its kernels (fused bottom launches or separate ones, as
     for FP64 Q4) up to rounding order, and the oracle's V-cycle; also after
-    a change of kappa (the operator is scaled, not rebuilt).  Where no
-    operator is built (no level between 0 and L; Full smoother) both
-    switches give the kernels bitwise."""
+    a change of kappa (the operator is scaled, not rebuilt); for every
+    smoother variant, the Full one included.  Where no operator is built
+    (no level between 0 and L) both switches give the kernels bitwise."""
     note(f"dense bottom d={dim} k={k} L={L} fp{precision} variant={variant}")
     prob = dgmg.Problem(dim, k, L, precision=precision, variant=variant, nrhs_max=3)
     assert prob.dense_bottom_level() == level
