@@ -405,3 +405,36 @@ def test_adjoint_dense_and_closed_form_and_fd():
     lp = dense_adjoint(A1, kappa, b + e, ut)[1]
     lm = dense_adjoint(A1, kappa, b - e, ut)[1]
     assert abs((lp - lm) / (2 * eps) - lam[j]) <= 1e-6 * np.abs(lam).max()
+
+
+@pytest.mark.parametrize("d,k,L,m,mode", [(2, 1, 3, 1, "exact"), (2, 2, 3, 2, "local"), (3, 1, 2, 1, "exact"),
+                                          (2, 1, 3, 2, "full"), (2, 3, 2, 1, "clamped")])
+def test_vcycle_bottom_is_a_fixed_linear_map(d, k, L, m, mode):
+    """The cycle below a level m is linear in its right-hand side and scales
+    as 1/kappa (A(kappa) = kappa A_1), so it equals the matrix of its action
+    on the unit vectors of level m; the cycle from L with that matrix in
+    place of the recursion below m is the V-cycle (the premise of applying
+    the bottom levels as a stored dense operator)."""
+    H = Hierarchy(d, k, L, sig(k), mode=mode)
+    rng = np.random.default_rng(31)
+    nm = H.ndofs(m)
+    u, v = rng.standard_normal(nm), rng.standard_normal(nm)
+    lhs = H.vcycle(2.5 * u - v, m)
+    rhs = 2.5 * H.vcycle(u, m) - H.vcycle(v, m)
+    assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(rhs)
+    Hk = Hierarchy(d, k, L, sig(k), kappa=0.37, mode=mode)
+    assert np.linalg.norm(Hk.vcycle(u, m) - H.vcycle(u, m) / 0.37) <= 1e-12 * np.linalg.norm(H.vcycle(u, m))
+    D = np.stack([H.vcycle(e, m) for e in np.eye(nm)], axis=1)
+
+    class DenseBottom(Hierarchy):
+        def vcycle(self, b, l=None):
+            l = self.L if l is None else l
+            return D @ b if l == m else super().vcycle(b, l)
+
+    Hd = DenseBottom(d, k, L, sig(k), mode=mode)
+    b = rng.standard_normal(H.ndofs(L))
+    ref = H.vcycle(b)
+    assert np.linalg.norm(Hd.vcycle(b) - ref) <= 1e-12 * np.linalg.norm(ref)
+    # a planted mistake in the stored matrix (one column) is seen
+    D[:, 0] *= 2.0
+    assert np.linalg.norm(Hd.vcycle(b) - ref) > 1e-8 * np.linalg.norm(ref)
