@@ -393,15 +393,18 @@ __device__ __forceinline__ void line_S_t(const Tab<K, T>* __restrict__ t, const 
   using B = FDB<SP, TY>;
   const T* S = fd_S<T, SP>(t, TY);
   if constexpr (kEO && SP == SP_DIR && TY == 0) {
-    o.v[0] = T(0);
-    o.v[E - 1] = T(0);
+    // outputs written in increasing node order, as in the other types: the
+    // compiler then merges the four type branches' stores into one line
+    // without a runtime-indexed copy of it (which would live in scratch)
+    T e[kEOH], d[kEOH];
 #pragma unroll
-    for (int k = 0; k < kEOH; ++k) {
-      T e, d;
-      eo_pair<T>(S, v, k, e, d);
-      o.v[1 + k] = e + d;
-      o.v[E - 2 - k] = e - d;
-    }
+    for (int k = 0; k < kEOH; ++k) eo_pair<T>(S, v, k, e[k], d[k]);
+    o.v[0] = T(0);
+#pragma unroll
+    for (int k = 0; k < kEOH; ++k) o.v[1 + k] = e[k] + d[k];
+#pragma unroll
+    for (int k = kEOH - 1; k >= 0; --k) o.v[E - 2 - k] = e[k] - d[k];
+    o.v[E - 1] = T(0);
     return;
   }
 #pragma unroll
@@ -602,20 +605,20 @@ __device__ __forceinline__ void gather_ext(const Tab<K, T>* __restrict__ t, cons
     const int side = (i / NF) & 1;
     const int fd = i / (2 * NF) + FD0;
     const int dir = fd + 1;
-    const int nb = (side == 0) ? P.lo[dir] - 1 : P.lo[dir] + 2;
+    const int lod = (dir == 1) ? P.lo[1] : P.lo[2];  // not P.lo[dir]: no scratch copy of P
+    const int nb = (side == 0) ? lod - 1 : lod + 2;
     T alpha = T(0), beta = T(0);
     if (MODE != 2 && nb >= 0 && nb < N) {
+      // neighbour cell and the face node's local coordinates in it (tangential
+      // coordinates from (a, b), 0 along dir); named per direction rather than
+      // indexed by the runtime dir, which would put the arrays in scratch
       const int a = f % E, b = f / E;
-      int cc[3], ac[3];
-      cc[0] = P.lo[0] + a / n;
-      ac[0] = a % n;
-      if (dir == 1) { cc[2] = P.lo[2] + b / n; ac[2] = b % n; }
-      else { cc[1] = P.lo[1] + b / n; ac[1] = b % n; }
-      if (D == 2) { cc[2] = 0; ac[2] = 0; }
-      cc[dir] = nb;
-      ac[dir] = 0;
+      const int cx = P.lo[0] + a / n, ax = a % n;
+      const int cy = (dir == 1) ? nb : P.lo[1] + b / n, ay = (dir == 1) ? 0 : b % n;
+      const int cz = (D == 2) ? 0 : (dir == 1) ? P.lo[2] + b / n : nb;
+      const int az = (D == 2 || dir != 1) ? 0 : b % n;
       const int strideN = (dir == 1) ? n : n * n;
-      const long long base = cell_index(N, cc[0], cc[1], cc[2]) * NC + ac[0] + n * (ac[1] + n * ac[2]);
+      const long long base = cell_index(N, cx, cy, cz) * NC + ax + n * (ay + n * az);
       const T tr = x[base + (long long)((side == 0) ? K : 0) * strideN];
       beta = (side == 0) ? -half * tr : half * tr;
       if (MODE == 0) {
@@ -1082,6 +1085,16 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
       }
       mass_row<T>(q % n, rowz);
     }
+    // patches of several waves (no register z-faces): this lane's z-face node
+    // (px, q) on both z-neighbours, the traces gather_ext would read
+    T ztr0 = T(0), ztr1 = T(0);
+    if constexpr (D == 3 && !RFZ && MODE == 1) {
+      static_assert(NF == TPP, "one z-face node per lane");
+      const int cx = P.lo[0] + px / n, cy = P.lo[1] + q / n;
+      const long long o = px % n + (long long)n * (q % n);
+      ztr0 = x[cell_index(N, cx, cy, P.lo[2] > 0 ? P.lo[2] - 1 : P.lo[2]) * NC + o + K * n * n];
+      ztr1 = x[cell_index(N, cx, cy, P.lo[2] + 2 < N ? P.lo[2] + 2 : P.lo[2]) * NC + o];
+    }
     const int py = lane % E, pz = lane / E;
     const long long row0 = xrow_offset(N, P, py, pz);
     read_xline<T>(x, row0, xl);
@@ -1106,8 +1119,11 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
         for (int nu = 0; nu < n; ++nu) s += yraw.row[nu] * (half * zr[nu]);
         wz1 = s;
       }
-    } else if constexpr (!RFZ) {
-      gather_ext<T, MODE>(t, x, N, P, lane, ext);
+    } else if constexpr (!RFZ && D == 3) {
+      // the z-face traces as gather_ext stores them (zeros for MODE 2)
+      const T half = T(0.5);
+      ext[lane] = (MODE == 1 && P.lo[2] > 0) ? -half * ztr0 : T(0);
+      ext[NF + lane] = (MODE == 1 && P.lo[2] + 2 < N) ? half * ztr1 : T(0);
     }
     Sides<T> sd;
     sd.bl = xbl;
@@ -1742,8 +1758,12 @@ __device__ __forceinline__ void smooth_body(const Tab<K, T>* __restrict__ t, con
     }
   }
   const int tyx = P.ty[0], tyy = P.ty[1], tyz = P.ty[2];
-  T rsl[E];  // inverse eigenvalue sums of the lane's scaling line
-  if (active) load_rs<T, SP>(t, P.ty, lane, rsl);
+  // inverse eigenvalue sums of the lane's scaling line: read at the start in
+  // 2-D (used by the first contraction phase), in 3-D only once the residual
+  // is formed, so that they are not held through the operator passes (the
+  // loads still overlap the X1 phase)
+  T rsl[E];
+  if (D == 2 && active) load_rs<T, SP>(t, P.ty, lane, rsl);
   Line<T> xl;  // the thread's x-line of x, kept for the final update
   // y-face couplings of the thread's y-line, read early from global (Dirichlet
   // kernels), and (PREFETCH) its line of b for the last operator pass: one
@@ -1780,6 +1800,7 @@ __device__ __forceinline__ void smooth_body(const Tab<K, T>* __restrict__ t, con
   }
   __syncthreads();
   if constexpr (D == 3) {
+    if (active) load_rs<T, SP>(t, P.ty, lane, rsl);
     // X1: S_x^T
     if (active)
       for (int i = lane; i < NL; i += TPP) {
@@ -2123,12 +2144,6 @@ __device__ __forceinline__ void smooth_split_body(const Tab<K, T>* __restrict__ 
   Half<T> xh;  // this half of the thread's x-line of x
   Half<T> bh;  // this half of the thread's z-line of b
   T rsh[n];    // inverse eigenvalue sums of this half of the lane's scaling line
-  if (active) {
-    T rsl[E];
-    load_rs<T, SP>(t, P.ty, lane, rsl);
-#pragma unroll
-    for (int j = 0; j < n; ++j) rsh[j] = rsl[H * n + j];
-  }
   if (PREFETCH && active) read_lasthalf<T>(br, g.N, P, lane, H, bh);
   if constexpr (ZERO) {
 #pragma unroll
@@ -2191,22 +2206,20 @@ __device__ __forceinline__ void smooth_split_body(const Tab<K, T>* __restrict__ 
         }
       }
     } else {
+      // this lane's z-face entry (face node lane, side H), its load issued
+      // before the y-side loads so that both arrive in one round trip
+      const int znb = (H == 0) ? P.lo[2] - 1 : P.lo[2] + 2;
+      const bool zhas = MODE == 1 && znb >= 0 && znb < g.N;
+      T ztr = T(0);
+      if (active && MODE == 1) {
+        const int a = lane % E, bb = lane / E;
+        const long long base = cell_index(g.N, P.lo[0] + a / n, P.lo[1] + bb / n, zhas ? znb : P.lo[2]) * NC +
+                               a % n + n * (bb % n);
+        ztr = xr[base + (long long)((H == 0) ? K : 0) * n * n];
+      }
       if (active) ysd = yline_sides_global<T, OPM>(t, xr, g.N, P, lane % E, lane / E);
       if (active) {
-        for (int i = lane + H * TPP; i < 2 * NF; i += 2 * TPP) {
-          const int f = i % NF;
-          const int side = i / NF;
-          const int nb = (side == 0) ? P.lo[2] - 1 : P.lo[2] + 2;
-          T beta = T(0);
-          if (MODE == 1 && nb >= 0 && nb < g.N) {
-            const int a = f % E, bb = f / E;
-            const long long base = cell_index(g.N, P.lo[0] + a / n, P.lo[1] + bb / n, nb) * NC + a % n +
-                                   n * (bb % n);
-            const T tr = xr[base + (long long)((side == 0) ? K : 0) * n * n];
-            beta = (side == 0) ? -T(0.5) * tr : T(0.5) * tr;
-          }
-          ext[side * NF + f] = beta;
-        }
+        ext[H * NF + lane] = zhas ? ((H == 0) ? -T(0.5) * ztr : T(0.5) * ztr) : T(0);
         read_xline<T>(xr, row0, xl);
         sd = xline_sides<T, OPM>(t, xr, g.N, P, row0);
       }
@@ -2273,6 +2286,14 @@ __device__ __forceinline__ void smooth_split_body(const Tab<K, T>* __restrict__ 
       store_half(A, base, stride, H, bh);
     }
     __syncthreads();
+  }
+  // (the eigenvalue sums are read only now, not held through the residual
+  // passes; their loads overlap the next two phases)
+  if (active) {
+    T rsl[E];
+    load_rs<T, SP>(t, P.ty, lane, rsl);
+#pragma unroll
+    for (int j = 0; j < n; ++j) rsh[j] = rsl[H * n + j];
   }
   // S_z^T over the whole residual line -> B
   if (active) {
