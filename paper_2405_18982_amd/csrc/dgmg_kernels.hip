@@ -600,10 +600,15 @@ __device__ __forceinline__ void gather_ext(const Tab<K, T>* __restrict__ t, cons
   constexpr int FD0 = (MODE == 0) ? 0 : 1;  // smoothers read y-face traces from global
   const T half = T(0.5);
   const T sg = t->sigma;
-  for (int i = lane; i < (D - 1 - FD0) * 2 * NF; i += TPP) {
-    const int f = i % NF;
-    const int side = (i / NF) & 1;
-    const int fd = i / (2 * NF) + FD0;
+  // a patch face has one node per lane (NF = TPP), so entry block it = (fd -
+  // FD0) * 2 + side holds this lane's face node f = lane: unrolled, direction
+  // and side are compile-time constants of each block
+  static_assert(NF == TPP, "one face node per lane");
+#pragma unroll
+  for (int it = 0; it < (D - 1 - FD0) * 2; ++it) {
+    const int f = lane;
+    const int side = it & 1;
+    const int fd = it / 2 + FD0;
     const int dir = fd + 1;
     const int lod = (dir == 1) ? P.lo[1] : P.lo[2];  // not P.lo[dir]: no scratch copy of P
     const int nb = (side == 0) ? lod - 1 : lod + 2;
