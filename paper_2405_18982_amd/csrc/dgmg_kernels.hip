@@ -1255,8 +1255,12 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
   if constexpr (D == 3) {
     // Y: c = M_y b + L_y a -> B, d = M_y a -> A; z-face data contracted along x
     if (active) {
-      for (int i = lane; i < NL + ((RFZ || RFA) ? 0 : 2 * NCOMP * E); i += TPP) {
-        if (i < NL) {
+      // one y-line per lane (NL = TPP), then, without register face data,
+      // lanes 0 .. 2 NCOMP E - 1 contract one z-face row each along x (the
+      // z-face arrays; the y-lines read only the y-face arrays of ext)
+      {
+        const int i = lane;
+        {
           const int px = i % E, pz = i / E;
           int base, stride;
           line_geom(1, i, base, stride);
@@ -1280,10 +1284,10 @@ __device__ __forceinline__ void operator_passes(const Tab<K, T>* __restrict__ t,
           line_mass<T>(t, a, d, n0y, nEy);
           store_line(B, base, stride, c);
           store_line(A, base, stride, d);
-        } else {
-          extz_mass_x_line<T, NCOMP>(t, ext, i - NL);
         }
       }
+      if constexpr (!(RFZ || RFA))
+        if (lane < 2 * NCOMP * E) extz_mass_x_line<T, NCOMP>(t, ext, lane);
     }
     __syncthreads();
     // Z: y = M_z c + L_z d
