@@ -1424,21 +1424,26 @@ k_apply(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restri
 // 4 E^2 values elsewhere (Q7 in FP64: 78 KB instead of 86 KB, two patches per
 // CU instead of one).
 constexpr bool kApplyRF = (D == 3);
+constexpr int kApplyRFPP = 2 * TS + (kZShfl ? 0 : 4 * NF);
 
-template <typename T, int PPB, bool RP = false>
-__global__ void __launch_bounds__(TPP * PPB)
-k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
-           T* __restrict__ y, long long ndof) {
+template <typename T>
+__device__ __forceinline__ void restrict_tail(const PatchGrid& g, const PatchPos& P, T* A, T* __restrict__ bc,
+                                              long long ndof_c, int rhs, int lane, bool active);
+
+// One patch of the register-face operator (pid, right-hand side rhs; lane =
+// thread within the patch, A = its LDS).  RESTRICT = false: y = scale A x on
+// the patch cells.  RESTRICT = true: the residual restriction of k_restrict,
+// bc = P^T (b - scale A x) into the patch's coarse cell (y is bc there), with
+// the same values (the operator output and the P^T contractions in the same
+// order) on the smaller LDS footprint of this kernel.
+template <typename T, bool RESTRICT>
+__device__ __forceinline__ void apply_rf_body(const Tab<K, T>* t, const PatchGrid& g, T scale, const T* x, T* y,
+                                              const T* b, long long ndof, long long ndof_c, int pid, int lane,
+                                              T* A, int rhs) {
   // cross-lane reads stay within a patch's lanes, which lie in one wave
   static_assert(kApplyRF, "3-D only");
-  constexpr int PP = 2 * TS + (kZShfl ? 0 : 4 * NF);
-  __shared__ T smem[PPB * PP];
-  const int slot = slot_of(), lane = threadIdx.x % TPP;
   const int wl = threadIdx.x & 63;
-  int pid, rhs;
-  slot_work<PPB, RP>(g, slot, pid, rhs);
   const bool active = pid < g.npatch;
-  T* A = smem + slot * PP;
   T* B = A + TS;
   const long long roff = (long long)rhs * ndof;
   const T* xr = x + roff;
@@ -1627,22 +1632,50 @@ k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
     sd.lit = false;
     line_mass<T>(t, c, o);
     line_sipg<T, true>(t, d, sd, o);
+    if constexpr (RESTRICT) {
+      // r = b - scale A x on this z-line, contracted with P^T along z
+      Line<T> r;
+      read_lastline<T>(b + roff, N, P, lane, r);
 #pragma unroll
-    for (int p = 0; p < E; ++p) A[base + p * stride] = scale * o.v[p];
-  }
-  __syncthreads();
-  // X2: contiguous row stores
-  if (active) {
-    const int py = lane % E, pz = lane / E;
-    int base, stride;
-    line_geom(0, lane, base, stride);
-    const long long row0 = xrow_offset(N, P, py, pz);
+      for (int nu = 0; nu < n; ++nu) {
+        T s = T(0);
 #pragma unroll
-    for (int a = 0; a < n; ++a) {
-      yr[row0 + a] = A[base + a];
-      yr[row0 + NC + a] = A[base + n + a];
+        for (int p = 0; p < E; ++p) s += T(kRef.P[p * n + nu]) * (r.v[p] - scale * o.v[p]);
+        A[base + nu * stride] = s;
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < E; ++p) A[base + p * stride] = scale * o.v[p];
     }
   }
+  __syncthreads();
+  if constexpr (RESTRICT) {
+    restrict_tail<T>(g, P, A, y, ndof_c, rhs, lane, active);
+  } else {
+    // X2: contiguous row stores
+    if (active) {
+      const int py = lane % E, pz = lane / E;
+      int base, stride;
+      line_geom(0, lane, base, stride);
+      const long long row0 = xrow_offset(N, P, py, pz);
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        yr[row0 + a] = A[base + a];
+        yr[row0 + NC + a] = A[base + n + a];
+      }
+    }
+  }
+}
+
+template <typename T, int PPB, bool RP = false>
+__global__ void __launch_bounds__(TPP * PPB)
+k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
+           T* __restrict__ y, long long ndof) {
+  __shared__ T smem[PPB * kApplyRFPP];
+  const int slot = slot_of(), lane = threadIdx.x % TPP;
+  int pid, rhs;
+  slot_work<PPB, RP>(g, slot, pid, rhs);
+  apply_rf_body<T, false>(t, g, scale, x, y, nullptr, ndof, 0, pid, lane, smem + slot * kApplyRFPP, rhs);
 }
 
 // ----------------------------------------------------------------- mass
@@ -2437,6 +2470,15 @@ __device__ __forceinline__ void restrict_body(const Tab<K, T>* __restrict__ t, c
                           }
                         });
   __syncthreads();
+  restrict_tail<T>(g, P, A, bc, ndof_c, rhs, lane, active);
+}
+
+// The restriction after the last direction (its P^T values at the first n
+// nodes of each last-direction line of A): P^T along y (3-D), then along x
+// into the rows of the patch's coarse cell of bc.
+template <typename T>
+__device__ __forceinline__ void restrict_tail(const PatchGrid& g, const PatchPos& P, T* A, T* __restrict__ bc,
+                                              long long ndof_c, int rhs, int lane, bool active) {
   if constexpr (D == 3) {
     // restrict along y: lines (px, pz < n)
     if (active)
@@ -2484,6 +2526,22 @@ k_restrict(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
   const int slot = slot_of(), lane = threadIdx.x % TPP;
   const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
   restrict_body<T>(t, g, scale, x, b, bc, ndof, ndof_c, pid, lane, smem + slot * kRestrictPP, blockIdx.y);
+}
+
+// 3-D degrees whose patches span several waves (or do not divide one): the
+// same restriction on the register-face operator of k_apply_rf, whose LDS
+// holds two tiles and four z-face rows instead of the face arrays (3-D Q7 in
+// FP64: two patches per CU instead of one)
+constexpr bool kRestrictOnApplyRF = kApplyRF && !kRestrictRF;
+template <typename T, int PPB>
+__global__ void __launch_bounds__(TPP * PPB)
+k_restrict_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restrict__ x,
+              const T* __restrict__ b, T* __restrict__ bc, long long ndof, long long ndof_c) {
+  __shared__ T smem[PPB * kApplyRFPP];
+  const int slot = slot_of(), lane = threadIdx.x % TPP;
+  const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
+  apply_rf_body<T, true>(t, g, scale, x, bc, b, ndof, ndof_c, pid, lane, smem + slot * kApplyRFPP,
+                         blockIdx.y);
 }
 
 // ------------------------------------------------- prolongation + add
@@ -2842,7 +2900,7 @@ constexpr int rpack_slots() {
 }
 template <typename T>
 constexpr int rpack_apply_slots() {
-  return kApplyRF ? rpack_slots<T, 2 * TS + (kZShfl ? 0 : 4 * NF)>()
+  return kApplyRF ? rpack_slots<T, kApplyRFPP>()
                   : rpack_slots<T, Smem<2, (D - 1) * 2 * 2 * NF>::per_patch>();
 }
 
@@ -3018,8 +3076,12 @@ hipError_t launch_restrict(const void* tab, PatchGrid g, T scale, const T* x, co
                            int nrhs, long long ndof, long long ndof_c, hipStream_t s) {
   constexpr int PPB = PPB_DEFAULT;
   dim3 grid((g.npatch + PPB - 1) / PPB, nrhs);
-  hipLaunchKernelGGL((k_restrict<T, PPB>), grid, dim3(TPP * PPB), 0, s,
-                     (const Tab<K, T>*)tab, g, scale, x, b, bc, ndof, ndof_c);
+  if constexpr (kRestrictOnApplyRF)
+    hipLaunchKernelGGL((k_restrict_rf<T, PPB>), grid, dim3(TPP * PPB), 0, s,
+                       (const Tab<K, T>*)tab, g, scale, x, b, bc, ndof, ndof_c);
+  else
+    hipLaunchKernelGGL((k_restrict<T, PPB>), grid, dim3(TPP * PPB), 0, s,
+                       (const Tab<K, T>*)tab, g, scale, x, b, bc, ndof, ndof_c);
   return hipGetLastError();
 }
 template <typename T>

@@ -164,6 +164,24 @@ def test_restrict_and_prolongate(dim, k, L):
             close(Xp[j], X[j] + P @ Xc[j])
 
 
+@pytest.mark.parametrize("dim,k,L", [(3, 2, 3), (3, 4, 2), (3, 5, 1), (3, 6, 1)])
+def test_restrict_residual_register_face_degrees(dim, k, L):
+    # 3-D degrees whose restriction runs on the register-face operator: every
+    # level, three right-hand sides, interior and boundary patches
+    note(f"restrict d={dim} k={k} L={L}")
+    prob = problem(dim, k, L, nrhs_max=4)
+    sig = inputs.sigma_of(k)
+    for l in range(1, L + 1):
+        N = 2 ** (l + 1)
+        A = kron_operator(dim, k, N, sig)
+        P = prolongation(dim, k, N // 2)
+        X = inputs.uniform(700 + l, (3, prob.ndofs(l)))
+        B = inputs.uniform(800 + l, (3, prob.ndofs(l)))
+        Bc = host(prob.restrict_residual(cuda(X), cuda(B), level=l))
+        for j in range(3):
+            close(Bc[j], P.T @ (B[j] - A @ X[j]))
+
+
 @pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (2, 5), (3, 1), (3, 3), (3, 7)])
 def test_coarse_solve(dim, k):
     note(f"coarse d={dim} k={k}")
