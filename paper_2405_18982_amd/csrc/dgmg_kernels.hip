@@ -1750,9 +1750,14 @@ k_mass(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restric
 // row is written (zeros outside V_j), so x needs no clearing beforehand.
 // LDS per patch of the smoother: operator face data (full rows) for the Full
 // kernel, z-face traces only for the Dirichlet and clamped kernels
+// The Full kernel's operator pass on patches within one wave (3-D Q1, Q3)
+// takes the neighbour face data in registers, as the restriction does there:
+// two tiles of LDS per patch, no face arrays.
+constexpr bool kFullRF = (D == 3) && kZShfl && kXShfl;
 template <int MODE>
 __host__ __device__ constexpr int smooth_pp() {
-  return MODE == 3 ? Smem<2, (D - 1) * 2 * 2 * NF>::per_patch : Smem<2, (D - 2) * 2 * NF>::per_patch;
+  return MODE == 3 ? (kFullRF ? 2 * TS : Smem<2, (D - 1) * 2 * 2 * NF>::per_patch)
+                   : Smem<2, (D - 2) * 2 * NF>::per_patch;
 }
 
 // One patch (pid of grid g, right-hand side rhs) of one colour; lane = thread
@@ -1829,7 +1834,7 @@ __device__ __forceinline__ void smooth_body(const Tab<K, T>* __restrict__ t, con
     if (PREFETCH && active) read_lastline<T>(br, g.N, P, lane, bline);
 
     // residual r = b - A x on the last pass, contracted with S^T of that direction
-    operator_passes<T, OPM>(t, xr, g.N, P, A, B, ext, lane, active, xl,
+    operator_passes<T, OPM, FULL && kFullRF>(t, xr, g.N, P, A, B, ext, lane, active, xl,
                             [&](int l, int base, int stride, const Line<T>& v) {
                               Line<T> r, o;
                               if (PREFETCH) r = bline;
