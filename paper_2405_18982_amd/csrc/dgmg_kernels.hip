@@ -1447,7 +1447,6 @@ __device__ __forceinline__ void apply_rf_body(const Tab<K, T>* t, const PatchGri
   T* B = A + TS;
   const long long roff = (long long)rhs * ndof;
   const T* xr = x + roff;
-  T* yr = y + roff;
   const int N = g.N;
   const PatchPos P = patch_pos(g, active ? pid : 0);
   // lane = px + E q: y-line (px, pz = q), z-face node (px, py = q)
@@ -1654,6 +1653,7 @@ __device__ __forceinline__ void apply_rf_body(const Tab<K, T>* t, const PatchGri
   } else {
     // X2: contiguous row stores
     if (active) {
+      T* yr = y + roff;
       const int py = lane % E, pz = lane / E;
       int base, stride;
       line_geom(0, lane, base, stride);
