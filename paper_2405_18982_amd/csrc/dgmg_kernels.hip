@@ -1431,19 +1431,24 @@ __device__ __forceinline__ void restrict_tail(const PatchGrid& g, const PatchPos
                                               long long ndof_c, int rhs, int lane, bool active);
 
 // One patch of the register-face operator (pid, right-hand side rhs; lane =
-// thread within the patch, A = its LDS).  RESTRICT = false: y = scale A x on
-// the patch cells.  RESTRICT = true: the residual restriction of k_restrict,
-// bc = P^T (b - scale A x) into the patch's coarse cell (y is bc there), with
-// the same values (the operator output and the P^T contractions in the same
-// order) on the smaller LDS footprint of this kernel.
-template <typename T, bool RESTRICT>
+// thread within the patch, A = its LDS, active: the patch takes part; xl
+// returns the lane's x-line of x).  What follows the operator's last pass:
+//   RF_APPLY: y = scale A x on the patch cells;
+//   RF_RESTRICT: the residual restriction of k_restrict, bc = P^T (b - scale
+//     A x) into the patch's coarse cell (y is bc there), with the same values
+//     (the operator output and the P^T contractions in the same order);
+//   RF_EMIT: emit(l, base, stride, v) with the operator output v of z-line l
+//     (as operator_passes hands it to the Full smoother), nothing after it.
+// All on the smaller LDS footprint of this kernel (two tiles, plus four
+// z-face rows where patches span several waves).
+constexpr int RF_APPLY = 0, RF_RESTRICT = 1, RF_EMIT = 2;
+template <typename T, int OUT, typename Emit = int>
 __device__ __forceinline__ void apply_rf_body(const Tab<K, T>* t, const PatchGrid& g, T scale, const T* x, T* y,
                                               const T* b, long long ndof, long long ndof_c, int pid, int lane,
-                                              T* A, int rhs) {
+                                              T* A, int rhs, bool active, Line<T>& xl, Emit emit = 0) {
   // cross-lane reads stay within a patch's lanes, which lie in one wave
   static_assert(kApplyRF, "3-D only");
   const int wl = threadIdx.x & 63;
-  const bool active = pid < g.npatch;
   T* B = A + TS;
   const long long roff = (long long)rhs * ndof;
   const T* xr = x + roff;
@@ -1462,7 +1467,6 @@ __device__ __forceinline__ void apply_rf_body(const Tab<K, T>* t, const PatchGri
   T nya0 = T(0), nyb0 = T(0), nya1 = T(0), nyb1 = T(0);
   T nza0 = T(0), nzb0 = T(0), nza1 = T(0), nzb1 = T(0);
   const int nuo = px % n;
-  Line<T> xl;
   if (!kXShfl && active) {
     // x-blocks straddle waves: each lane reads whole face blocks
     const int cx = P.lo[0] + px / n;
@@ -1631,7 +1635,9 @@ __device__ __forceinline__ void apply_rf_body(const Tab<K, T>* t, const PatchGri
     sd.lit = false;
     line_mass<T>(t, c, o);
     line_sipg<T, true>(t, d, sd, o);
-    if constexpr (RESTRICT) {
+    if constexpr (OUT == RF_EMIT) {
+      emit(lane, base, stride, o);
+    } else if constexpr (OUT == RF_RESTRICT) {
       // r = b - scale A x on this z-line, contracted with P^T along z
       Line<T> r;
       read_lastline<T>(b + roff, N, P, lane, r);
@@ -1647,8 +1653,9 @@ __device__ __forceinline__ void apply_rf_body(const Tab<K, T>* t, const PatchGri
       for (int p = 0; p < E; ++p) A[base + p * stride] = scale * o.v[p];
     }
   }
+  if constexpr (OUT == RF_EMIT) return;  // the caller's barrier follows
   __syncthreads();
-  if constexpr (RESTRICT) {
+  if constexpr (OUT == RF_RESTRICT) {
     restrict_tail<T>(g, P, A, y, ndof_c, rhs, lane, active);
   } else {
     // X2: contiguous row stores
@@ -1675,7 +1682,9 @@ k_apply_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __res
   const int slot = slot_of(), lane = threadIdx.x % TPP;
   int pid, rhs;
   slot_work<PPB, RP>(g, slot, pid, rhs);
-  apply_rf_body<T, false>(t, g, scale, x, y, nullptr, ndof, 0, pid, lane, smem + slot * kApplyRFPP, rhs);
+  Line<T> xl;
+  apply_rf_body<T, RF_APPLY>(t, g, scale, x, y, nullptr, ndof, 0, pid, lane, smem + slot * kApplyRFPP, rhs,
+                             pid < g.npatch, xl);
 }
 
 // ----------------------------------------------------------------- mass
@@ -1750,13 +1759,16 @@ k_mass(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __restric
 // row is written (zeros outside V_j), so x needs no clearing beforehand.
 // LDS per patch of the smoother: operator face data (full rows) for the Full
 // kernel, z-face traces only for the Dirichlet and clamped kernels
-// The Full kernel's operator pass on patches within one wave (3-D Q1, Q3)
-// takes the neighbour face data in registers, as the restriction does there:
-// two tiles of LDS per patch, no face arrays.
+// The Full kernel's operator pass takes the neighbour face data in registers
+// in 3-D, as the apply and the restriction do: on patches within one wave (Q1,
+// Q3) through operator_passes (two tiles of LDS per patch), otherwise through
+// the apply's register-face body (two tiles and four z-face rows); no face
+// arrays either way.
 constexpr bool kFullRF = (D == 3) && kZShfl && kXShfl;
+constexpr bool kFullOnApplyRF = kApplyRF && !kFullRF;
 template <int MODE>
 __host__ __device__ constexpr int smooth_pp() {
-  return MODE == 3 ? (kFullRF ? 2 * TS : Smem<2, (D - 1) * 2 * 2 * NF>::per_patch)
+  return MODE == 3 ? (kFullRF ? 2 * TS : kFullOnApplyRF ? kApplyRFPP : Smem<2, (D - 1) * 2 * 2 * NF>::per_patch)
                    : Smem<2, (D - 2) * 2 * NF>::per_patch;
 }
 
@@ -1834,16 +1846,19 @@ __device__ __forceinline__ void smooth_body(const Tab<K, T>* __restrict__ t, con
     if (PREFETCH && active) read_lastline<T>(br, g.N, P, lane, bline);
 
     // residual r = b - A x on the last pass, contracted with S^T of that direction
-    operator_passes<T, OPM, FULL && kFullRF>(t, xr, g.N, P, A, B, ext, lane, active, xl,
-                            [&](int l, int base, int stride, const Line<T>& v) {
-                              Line<T> r, o;
-                              if (PREFETCH) r = bline;
-                              else read_lastline<T>(br, g.N, P, l, r);
+    auto emit = [&](int l, int base, int stride, const Line<T>& v) {
+      Line<T> r, o;
+      if (PREFETCH) r = bline;
+      else read_lastline<T>(br, g.N, P, l, r);
 #pragma unroll
-                              for (int p = 0; p < E; ++p) r.v[p] -= scale * v.v[p];
-                              line_St<T, SP>(t, (D == 3) ? tyz : tyy, r, o);
-                              store_line(A, base, stride, o);
-                            });
+      for (int p = 0; p < E; ++p) r.v[p] -= scale * v.v[p];
+      line_St<T, SP>(t, (D == 3) ? tyz : tyy, r, o);
+      store_line(A, base, stride, o);
+    };
+    if constexpr (FULL && kFullOnApplyRF)
+      apply_rf_body<T, RF_EMIT>(t, g, scale, xin, nullptr, nullptr, ndof, 0, pid, lane, A, rhs, active, xl, emit);
+    else
+      operator_passes<T, OPM, FULL && kFullRF>(t, xr, g.N, P, A, B, ext, lane, active, xl, emit);
   }
   __syncthreads();
   if constexpr (D == 3) {
@@ -2545,8 +2560,9 @@ k_restrict_rf(const Tab<K, T>* __restrict__ t, PatchGrid g, T scale, const T* __
   __shared__ T smem[PPB * kApplyRFPP];
   const int slot = slot_of(), lane = threadIdx.x % TPP;
   const int pid = xcd_block(blockIdx.x, gridDim.x, g.xcd_remap) * PPB + slot;
-  apply_rf_body<T, true>(t, g, scale, x, bc, b, ndof, ndof_c, pid, lane, smem + slot * kApplyRFPP,
-                         blockIdx.y);
+  Line<T> xl;
+  apply_rf_body<T, RF_RESTRICT>(t, g, scale, x, bc, b, ndof, ndof_c, pid, lane, smem + slot * kApplyRFPP,
+                                blockIdx.y, pid < g.npatch, xl);
 }
 
 // ------------------------------------------------- prolongation + add
